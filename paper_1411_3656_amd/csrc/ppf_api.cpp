@@ -1,0 +1,326 @@
+// C-ABI layer of libppf.so: argument validation, plan objects, streams.
+//
+// Every entry point validates its arguments before the first HIP call,
+// catches every C++ exception, and records failures in a thread-local
+// status and message (ppf_last_error / ppf_last_error_message).
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ppf.h"
+#include "ppf_internal.h"
+
+namespace {
+
+thread_local int g_status = PPF_OK;
+thread_local char g_message[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  g_status = status;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_message, sizeof g_message, fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  const int st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PPF_ERR_NOMEM : PPF_ERR_HIP;
+  return fail(st, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int sample_bytes(int dtype) {
+  switch (dtype) {
+    case PPF_C32: return 8;
+    case PPF_C16: return 4;
+    case PPF_CI8: return 2;
+    default: return 0;
+  }
+}
+
+bool overlaps(uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; }
+
+// Largest FIR workspace of the two-pass path, in bytes (stays inside the
+// 256 MB Infinity Cache between the FIR and the FFT launch of a chunk).
+constexpr size_t kWorkspaceBytes = 64ull << 20;
+
+}  // namespace
+
+struct ppf_plan_s {
+  int N = 0, T = 0, TP = 0;
+  int in_type = PPF_C32, coeff_type = PPF_R32, coeff_shift = 0, fft_mode = PPF_FFT_F32;
+  int path = PPF_PATH_FUSED;
+  float* d_coef = nullptr;
+  float* d_ones = nullptr;
+  void* d_tw = nullptr;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  long long chunk_spectra = 0;
+  hipStream_t stream = nullptr;
+
+  ppf::PlanDev dev() const {
+    ppf::PlanDev p;
+    p.N = N;
+    p.T = T;
+    p.TP = TP;
+    p.coef = d_coef;
+    p.ones = d_ones;
+    p.tw = d_tw;
+    return p;
+  }
+  ~ppf_plan_s() {
+    if (d_coef) hipFree(d_coef);
+    if (d_ones) hipFree(d_ones);
+    if (d_tw) hipFree(d_tw);
+    if (d_ws) hipFree(d_ws);
+  }
+};
+
+struct ppf_stream_s {
+  ppf_plan_t plan = nullptr;
+  void* hist[2] = {nullptr, nullptr};   // ping-pong history buffers, (T-1)*N samples each
+  int cur = 0;
+  long long hist_samples = 0;
+  long long pushed_spectra = 0;
+  ~ppf_stream_s() {
+    if (hist[0]) hipFree(hist[0]);
+    if (hist[1]) hipFree(hist[1]);
+  }
+};
+
+namespace {
+
+int ensure_workspace(ppf_plan_t p) {
+  if (p->d_ws) return PPF_OK;
+  long long k = (long long)(kWorkspaceBytes / (8ull * p->N));
+  if (k < 1) k = 1;
+  p->chunk_spectra = k;
+  p->ws_bytes = (size_t)k * p->N * 8;
+  hipError_t e = hipMalloc(&p->d_ws, p->ws_bytes);
+  if (e != hipSuccess) {
+    p->d_ws = nullptr;
+    p->ws_bytes = 0;
+    return fail_hip(e, "workspace allocation");
+  }
+  return PPF_OK;
+}
+
+// FIR + FFT over M spectra of the concatenation x0 (h0 blocks) ++ x1.
+int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* out, long long M) {
+  const ppf::PlanDev pd = p->dev();
+  const size_t sb = (size_t)sample_bytes(p->in_type);
+  if (p->path == PPF_PATH_FUSED) {
+    ppf::BatchArgs a{x0, x1, h0, out, M};
+    hipError_t e = ppf::launch_fused(pd, a, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "fused kernel launch");
+    return PPF_OK;
+  }
+  int st = ensure_workspace(p);
+  if (st != PPF_OK) return st;
+  for (long long c0 = 0; c0 < M; c0 += p->chunk_spectra) {
+    const long long k = (M - c0 < p->chunk_spectra) ? (M - c0) : p->chunk_spectra;
+    // blocks c0 .. of the concatenation: split between x0 and x1
+    ppf::BatchArgs a;
+    if (c0 < h0) {
+      a.x0 = (const char*)x0 + (size_t)c0 * pd.N * sb;
+      a.h0 = h0 - c0;
+      a.x1 = x1;
+    } else {
+      a.x0 = x1;
+      a.h0 = 0;
+      a.x1 = (const char*)x1 + (size_t)(c0 - h0) * pd.N * sb;
+    }
+    a.out = p->d_ws;
+    a.M = k;
+    hipError_t e = ppf::launch_fir(pd, a, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
+    e = ppf::launch_fft(pd, p->d_ws, (char*)out + (size_t)c0 * pd.N * 8, k, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "FFT kernel launch");
+  }
+  return PPF_OK;
+}
+
+ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int coeff_shift, int in_type,
+                     int fft_mode) {
+  if (!coeffs) { fail(PPF_ERR_INVALID, "coeffs is NULL"); return nullptr; }
+  if (N < 1 || taps < 1) { fail(PPF_ERR_INVALID, "N=%d and taps=%d must be >= 1", N, taps); return nullptr; }
+  if (!is_pow2(N) || N < 16 || N > 16384) {
+    fail(PPF_ERR_UNSUPPORTED, "N=%d: supported N is a power of two in [16, 16384]", N);
+    return nullptr;
+  }
+  const int TP = ppf::taps_template(taps);
+  if (TP == 0) { fail(PPF_ERR_UNSUPPORTED, "taps=%d: supported taps are 1..64", taps); return nullptr; }
+  if (coeff_type != PPF_R32 && coeff_type != PPF_R16) {
+    fail(PPF_ERR_INVALID, "coeff_type=%d is not a real coefficient type", coeff_type);
+    return nullptr;
+  }
+  if (sample_bytes(in_type) == 0) { fail(PPF_ERR_INVALID, "in_type=%d is not a complex input type", in_type); return nullptr; }
+  if (fft_mode != PPF_FFT_F32 && fft_mode != PPF_FFT_MFMA_F16) {
+    fail(PPF_ERR_INVALID, "fft_mode=%d unknown", fft_mode);
+    return nullptr;
+  }
+  if (coeff_type == PPF_R32 && coeff_shift != 0) {
+    fail(PPF_ERR_INVALID, "coeff_shift must be 0 for float32 coefficients");
+    return nullptr;
+  }
+  if (coeff_shift < 0 || coeff_shift > 30) { fail(PPF_ERR_INVALID, "coeff_shift=%d outside 0..30", coeff_shift); return nullptr; }
+  if (coeff_type != PPF_R32 || in_type != PPF_C32 || fft_mode != PPF_FFT_F32) {
+    fail(PPF_ERR_UNSUPPORTED, "only float32 coefficients, complex float32 input and the FP32 FFT are built");
+    return nullptr;
+  }
+  if (!ppf::fft_available(N) || !ppf::fir_available(TP)) {
+    fail(PPF_ERR_UNSUPPORTED, "no kernel for N=%d taps=%d", N, taps);
+    return nullptr;
+  }
+
+  ppf_plan_s* p = new (std::nothrow) ppf_plan_s;
+  if (!p) { fail(PPF_ERR_NOMEM, "host allocation"); return nullptr; }
+  p->N = N;
+  p->T = taps;
+  p->TP = TP;
+  p->in_type = in_type;
+  p->coeff_type = coeff_type;
+  p->coeff_shift = coeff_shift;
+  p->fft_mode = fft_mode;
+  p->path = ppf::fused_available(N, TP) || TP == 1 ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+
+  // coefficients padded at the front with TP-T zero segments
+  std::vector<float> hpad((size_t)TP * N, 0.0f);
+  std::memcpy(hpad.data() + (size_t)(TP - taps) * N, coeffs, (size_t)taps * N * sizeof(float));
+  std::vector<float> ones((size_t)N, 1.0f);
+
+  hipError_t e;
+  if ((e = hipMalloc(&p->d_coef, hpad.size() * sizeof(float))) != hipSuccess) { p->d_coef = nullptr; goto hip_fail; }
+  if ((e = hipMalloc(&p->d_ones, ones.size() * sizeof(float))) != hipSuccess) { p->d_ones = nullptr; goto hip_fail; }
+  if ((e = hipMalloc(&p->d_tw, (size_t)N * 8)) != hipSuccess) { p->d_tw = nullptr; goto hip_fail; }
+  if ((e = hipMemcpy(p->d_coef, hpad.data(), hpad.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
+  if ((e = hipMemcpy(p->d_ones, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
+  if ((e = ppf::launch_twiddles(p->d_tw, N, nullptr)) != hipSuccess) goto hip_fail;
+  if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) goto hip_fail;
+  g_status = PPF_OK;
+  return p;
+
+hip_fail:
+  fail_hip(e, "plan creation");
+  delete p;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+ppf_plan_t ppf_plan(int n_channels, int taps, const float* coeffs) {
+  try {
+    return make_plan(n_channels, taps, coeffs, PPF_R32, 0, PPF_C32, PPF_FFT_F32);
+  } catch (...) {
+    fail(PPF_ERR_NOMEM, "unexpected exception in ppf_plan");
+    return nullptr;
+  }
+}
+
+ppf_plan_t ppf_plan_ex(int n_channels, int taps, const void* coeffs, int coeff_type, int coeff_shift,
+                       int in_type, int fft_mode) {
+  try {
+    return make_plan(n_channels, taps, coeffs, coeff_type, coeff_shift, in_type, fft_mode);
+  } catch (...) {
+    fail(PPF_ERR_NOMEM, "unexpected exception in ppf_plan_ex");
+    return nullptr;
+  }
+}
+
+int ppf_set_stream(ppf_plan_t plan, void* hip_stream) {
+  if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+  plan->stream = (hipStream_t)hip_stream;
+  return PPF_OK;
+}
+
+int ppf_plan_set_path(ppf_plan_t plan, int path) {
+  if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+  switch (path) {
+    case PPF_PATH_AUTO:
+      plan->path = ppf::fused_available(plan->N, plan->TP) || plan->TP == 1 ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+      return PPF_OK;
+    case PPF_PATH_FUSED:
+      if (!(ppf::fused_available(plan->N, plan->TP) || plan->TP == 1))
+        return fail(PPF_ERR_UNSUPPORTED, "no fused kernel for N=%d taps=%d", plan->N, plan->T);
+      plan->path = PPF_PATH_FUSED;
+      return PPF_OK;
+    case PPF_PATH_TWO_PASS:
+      plan->path = PPF_PATH_TWO_PASS;
+      return PPF_OK;
+    default:
+      return fail(PPF_ERR_INVALID, "path=%d unknown", path);
+  }
+}
+
+int ppf_plan_query(ppf_plan_t plan, int key, long long* value) {
+  if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+  if (!value) return fail(PPF_ERR_INVALID, "value is NULL");
+  switch (key) {
+    case PPF_Q_N: *value = plan->N; return PPF_OK;
+    case PPF_Q_TAPS: *value = plan->T; return PPF_OK;
+    case PPF_Q_PATH: *value = plan->path; return PPF_OK;
+    case PPF_Q_WORKSPACE_BYTES: *value = (long long)plan->ws_bytes; return PPF_OK;
+    case PPF_Q_IN_TYPE: *value = plan->in_type; return PPF_OK;
+    case PPF_Q_FFT_MODE: *value = plan->fft_mode; return PPF_OK;
+    case PPF_Q_COEFF_SHIFT: *value = plan->coeff_shift; return PPF_OK;
+    case PPF_Q_FUSED_AVAILABLE: *value = (ppf::fused_available(plan->N, plan->TP) || plan->TP == 1) ? 1 : 0; return PPF_OK;
+    default: return fail(PPF_ERR_INVALID, "query key %d unknown", key);
+  }
+}
+
+int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra) {
+  try {
+    if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+    if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
+    if (nspectra == 0) { g_status = PPF_OK; return PPF_OK; }
+    if (!in || !out) return fail(PPF_ERR_INVALID, "in or out is NULL");
+    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return fail(PPF_ERR_ALIGN, "in and out must be 16-byte aligned");
+    const size_t sb = (size_t)sample_bytes(plan->in_type);
+    const size_t in_bytes = (size_t)(nspectra + plan->T - 1) * plan->N * sb;
+    const size_t out_bytes = (size_t)nspectra * plan->N * 8;
+    if (overlaps((uintptr_t)in, in_bytes, (uintptr_t)out, out_bytes)) return fail(PPF_ERR_INVALID, "in and out overlap");
+    const int st = run_batch(plan, in, 0, in, out, nspectra);
+    if (st == PPF_OK) g_status = PPF_OK;
+    return st;
+  } catch (...) {
+    return fail(PPF_ERR_HIP, "unexpected exception in ppf_execute");
+  }
+}
+
+int ppf_destroy(ppf_plan_t plan) {
+  if (!plan) return PPF_OK;
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  delete plan;
+  if (e != hipSuccess) return fail_hip(e, "ppf_destroy synchronize");
+  return PPF_OK;
+}
+
+int ppf_last_error(void) { return g_status; }
+
+const char* ppf_last_error_message(void) { return g_message; }
+
+const char* ppf_status_str(int status) {
+  switch (status) {
+    case PPF_OK: return "PPF_OK";
+    case PPF_ERR_INVALID: return "PPF_ERR_INVALID";
+    case PPF_ERR_UNSUPPORTED: return "PPF_ERR_UNSUPPORTED";
+    case PPF_ERR_ALIGN: return "PPF_ERR_ALIGN";
+    case PPF_ERR_NOMEM: return "PPF_ERR_NOMEM";
+    case PPF_ERR_BUDGET: return "PPF_ERR_BUDGET";
+    case PPF_ERR_HIP: return "PPF_ERR_HIP";
+    case PPF_ERR_BUSY: return "PPF_ERR_BUSY";
+    default: return "PPF_ERR_UNKNOWN";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Internal interface between the C-ABI layer (ppf_api.cpp) and the HIP
+// kernels (ppf_kernels.hip). Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppf {
+
+// Launch description for one batch of spectra. The input is read as the
+// concatenation of two segments: x0 holds h0 blocks (a stream's history,
+// h0 = 0 for the plain batch form) and x1 the rest. Block b of the
+// concatenation is b*N samples in. The output of spectrum m (0 <= m < M)
+// goes to out + m*N.
+struct BatchArgs {
+  const void* x0;
+  const void* x1;
+  long long h0;        // blocks in x0
+  void* out;           // complex FP32 output (or the FIR workspace)
+  long long M;         // spectra to produce
+};
+
+// Plan-owned device constants used by the kernels.
+struct PlanDev {
+  int N;
+  int T;               // taps as given
+  int TP;              // taps rounded up to the kernel's template tap count
+  const float* coef;   // TP*N, zero-padded at the front (TP-T leading zero segments)
+  const float* ones;   // N ones: identity coefficients for the FFT-only pass
+  const void* tw;      // N complex FP32 twiddles exp(-2 pi i k/N)
+};
+
+int taps_template(int T);                       // smallest supported TP >= T, 0 if none
+bool fused_available(int N, int TP);
+bool fft_available(int N);
+bool fir_available(int TP);
+
+// One fused kernel over args.M spectra.
+hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
+// FIR presum only: writes u (complex FP32, M*N) to a.out.
+hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
+// Batched N-point FFT of M contiguous blocks (in x1) to a.out.
+hipError_t launch_fft(const PlanDev& pd, const void* in, void* out, long long M, hipStream_t st);
+// FP64 twiddle generation: tw[k] = exp(-2 pi i k/N) rounded to FP32.
+hipError_t launch_twiddles(void* tw, int N, hipStream_t st);
+// Stream history update: new = last `hist_samples` samples of (old ++ chunk).
+hipError_t launch_history(const void* old_hist, const void* chunk, void* new_hist,
+                          long long hist_samples, long long chunk_samples, int sample_bytes,
+                          hipStream_t st);
+
+}  // namespace ppf

@@ -1,0 +1,200 @@
+"""Thin ctypes binding of libppf.so (include/ppf.h), same names as the C ABI.
+
+Every function here only marshals arguments: all PPF arithmetic runs in the
+HIP library. Device buffers are passed as integer addresses (torch's
+``tensor.data_ptr()``) and HIP streams as integer handles (torch's
+``stream.cuda_stream``). Failures raise :class:`PPFError`; a missing
+library raises at load time, never falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+_LIB_PATH = pathlib.Path(__file__).resolve().with_name("libppf.so")
+_lib = None
+
+# status codes (enum ppf_status)
+PPF_OK = 0
+PPF_ERR_INVALID = -1
+PPF_ERR_UNSUPPORTED = -2
+PPF_ERR_ALIGN = -3
+PPF_ERR_NOMEM = -4
+PPF_ERR_BUDGET = -5
+PPF_ERR_HIP = -6
+PPF_ERR_BUSY = -7
+
+# element types (enum ppf_dtype)
+PPF_C32, PPF_C16, PPF_CI8, PPF_R32, PPF_R16 = 0, 1, 2, 3, 4
+# FFT modes, paths, queries
+PPF_FFT_F32, PPF_FFT_MFMA_F16 = 0, 1
+PPF_PATH_AUTO, PPF_PATH_FUSED, PPF_PATH_TWO_PASS = 0, 1, 2
+(PPF_Q_N, PPF_Q_TAPS, PPF_Q_PATH, PPF_Q_WORKSPACE_BYTES, PPF_Q_IN_TYPE, PPF_Q_FFT_MODE,
+ PPF_Q_COEFF_SHIFT, PPF_Q_FUSED_AVAILABLE) = range(8)
+
+SAMPLE_BYTES = {PPF_C32: 8, PPF_C16: 4, PPF_CI8: 2}
+
+_c_ll = ctypes.c_longlong
+_c_vp = ctypes.c_void_p
+_c_int = ctypes.c_int
+
+
+class PPFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_str(status)} ({status}): {message}")
+        self.status = status
+
+
+# (name, restype, argtypes) of every exported function
+_SIGNATURES = [
+    ("ppf_plan", _c_vp, [_c_int, _c_int, _c_vp]),
+    ("ppf_plan_ex", _c_vp, [_c_int, _c_int, _c_vp, _c_int, _c_int, _c_int, _c_int]),
+    ("ppf_set_stream", _c_int, [_c_vp, _c_vp]),
+    ("ppf_plan_set_path", _c_int, [_c_vp, _c_int]),
+    ("ppf_plan_query", _c_int, [_c_vp, _c_int, ctypes.POINTER(_c_ll)]),
+    ("ppf_execute", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
+    ("ppf_destroy", _c_int, [_c_vp]),
+    ("ppf_last_error", _c_int, []),
+    ("ppf_last_error_message", ctypes.c_char_p, []),
+    ("ppf_status_str", ctypes.c_char_p, [_c_int]),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libppf.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is not built: run `python -m paper_1411_3656_amd.build`")
+        handle = ctypes.CDLL(str(_LIB_PATH))
+        for name, res, args in _SIGNATURES:
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def library_path() -> pathlib.Path:
+    return _LIB_PATH
+
+
+def status_str(status: int) -> str:
+    try:
+        return lib().ppf_status_str(int(status)).decode()
+    except Exception:  # noqa: BLE001 - used while formatting an error
+        return str(status)
+
+
+def last_error() -> tuple[int, str]:
+    L = lib()
+    return int(L.ppf_last_error()), L.ppf_last_error_message().decode(errors="replace")
+
+
+def _check(status: int) -> int:
+    if status != PPF_OK:
+        code, msg = last_error()
+        raise PPFError(status, msg)
+    return status
+
+
+def _handle(h):
+    if not h:
+        code, msg = last_error()
+        raise PPFError(code, msg)
+    return h
+
+
+def _addr(buf) -> int | None:
+    """Address of a device buffer: an int, or an object with data_ptr()."""
+    if buf is None:
+        return None
+    if isinstance(buf, int):
+        return buf
+    return int(buf.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# the C ABI, name for name
+# ---------------------------------------------------------------------------
+
+def ppf_plan(n_channels: int, taps: int, coeffs) -> int:
+    """coeffs: host float32 array of taps*n_channels values (copied)."""
+    import numpy as np
+    h = np.ascontiguousarray(coeffs, dtype=np.float32)
+    if h.size != n_channels * taps:
+        raise ValueError("coeffs must hold taps*n_channels values")
+    return _handle(lib().ppf_plan(int(n_channels), int(taps), h.ctypes.data))
+
+
+def ppf_plan_ex(n_channels: int, taps: int, coeffs, coeff_type: int, coeff_shift: int,
+                in_type: int, fft_mode: int) -> int:
+    import numpy as np
+    dt = np.float32 if coeff_type == PPF_R32 else np.float16
+    h = np.ascontiguousarray(coeffs, dtype=dt)
+    return _handle(lib().ppf_plan_ex(int(n_channels), int(taps), h.ctypes.data, int(coeff_type),
+                                     int(coeff_shift), int(in_type), int(fft_mode)))
+
+
+def ppf_set_stream(plan: int, hip_stream) -> int:
+    return _check(lib().ppf_set_stream(plan, _addr(hip_stream) if hip_stream else None))
+
+
+def ppf_plan_set_path(plan: int, path: int) -> int:
+    return _check(lib().ppf_plan_set_path(plan, int(path)))
+
+
+def ppf_plan_query(plan: int, key: int) -> int:
+    v = _c_ll(0)
+    _check(lib().ppf_plan_query(plan, int(key), ctypes.byref(v)))
+    return int(v.value)
+
+
+def ppf_execute(plan: int, inp, out, nspectra: int) -> int:
+    return _check(lib().ppf_execute(plan, _addr(inp), _addr(out), int(nspectra)))
+
+
+def ppf_destroy(plan: int) -> int:
+    return _check(lib().ppf_destroy(plan))
+
+
+# ---------------------------------------------------------------------------
+# torch convenience (device memory and streams only)
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """Owning wrapper of a ppf_plan_t bound to torch's current stream."""
+
+    def __init__(self, n_channels: int, taps: int, coeffs, path: int = PPF_PATH_AUTO):
+        self.N, self.T = int(n_channels), int(taps)
+        self.handle = ppf_plan(self.N, self.T, coeffs)
+        if path != PPF_PATH_AUTO:
+            ppf_plan_set_path(self.handle, path)
+
+    @property
+    def path(self) -> int:
+        return ppf_plan_query(self.handle, PPF_Q_PATH)
+
+    def execute(self, x, out=None, nspectra: int | None = None, stream=None):
+        """x: complex64 CUDA tensor of (M+T-1)*N samples; returns (M, N) complex64."""
+        import torch
+        if nspectra is None:
+            nspectra = x.numel() // self.N - self.T + 1
+        if out is None:
+            out = torch.empty((nspectra, self.N), dtype=torch.complex64, device=x.device)
+        st = torch.cuda.current_stream(x.device) if stream is None else stream
+        ppf_set_stream(self.handle, st.cuda_stream)
+        ppf_execute(self.handle, x, out, nspectra)
+        return out
+
+    def close(self):
+        if self.handle:
+            ppf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

@@ -1,0 +1,188 @@
+"""HIP batch PPF against the FP64 oracle, element by element.
+
+Tolerance (stated by the workload definition): max |X - X_ref| over the
+checked outputs <= 1e-5 * RMS(X_ref) over the same outputs.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_3656_amd import ppf, signals
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+ALL_N = [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_err(got, ref):
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    return float(np.max(np.abs(got - ref))) / rms
+
+
+def run_gpu(x, h32, n, taps, path=ppf.PPF_PATH_AUTO, nspectra=None):
+    torch = _torch()
+    plan = ppf.Plan(n, taps, h32, path)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = plan.execute(xd, nspectra=nspectra)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    used = plan.path
+    plan.close()
+    return res, used
+
+
+def sample_spectra(m_total, taps, every=97):
+    idx = set(range(0, m_total, every))
+    idx.update(range(0, min(2 * taps, m_total)))
+    idx.update(range(max(0, m_total - 2 * taps), m_total))
+    return sorted(idx)
+
+
+def test_c1_plain_n256_full():
+    n, taps, m_total = 256, 8, 16384
+    print(f"case C1 N={n} T={taps} M={m_total}", flush=True)
+    h32 = signals.design_coeffs(n, taps, "hamming").astype(np.float32)
+    x = signals.plain_input(n, (m_total + taps - 1) * n, seed=signals.SEED_BASE + 0)
+    got, path = run_gpu(x, h32, n, taps)
+    ref = oracle.ppf(x, h32, n, taps)
+    assert got.shape == ref.shape == (m_total, n)
+    err = rel_err(got, ref)
+    print(f"C1 path={path} max err / rms = {err:.3e}")
+    assert err <= TOL
+
+
+def _small_case(n, taps, path, m_total, seed):
+    rng = np.random.default_rng(seed)
+    h32 = rng.standard_normal(taps * n).astype(np.float32)   # asymmetric: catches direction errors
+    x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed)
+    print(f"case small N={n} T={taps} path={path} M={m_total}", flush=True)
+    try:
+        got, used = run_gpu(x, h32, n, taps, path)
+    except ppf.PPFError as e:
+        if e.status == ppf.PPF_ERR_UNSUPPORTED:
+            pytest.skip(f"path {path} not built for N={n} T={taps}")
+        raise
+    ref = oracle.ppf(x, h32, n, taps)
+    err = rel_err(got, ref)
+    assert err <= TOL, (n, taps, path, used, err)
+    return used
+
+
+@pytest.mark.parametrize("path", [ppf.PPF_PATH_FUSED, ppf.PPF_PATH_TWO_PASS], ids=["fused", "twopass"])
+@pytest.mark.parametrize("taps", [1, 3, 8])
+@pytest.mark.parametrize("n", ALL_N)
+def test_small_shapes_ragged(n, taps, path):
+    # several tiles and a ragged tail; fewer spectra at the largest N
+    m_total = 203 if n <= 1024 else 37
+    used = _small_case(n, taps, path, m_total, seed=1000 + n + taps)
+    assert used == path
+
+
+@pytest.mark.parametrize("taps", [2, 4, 5, 16])
+@pytest.mark.parametrize("n", [64, 1024])
+def test_more_taps_auto_path(n, taps):
+    _small_case(n, taps, ppf.PPF_PATH_AUTO, 157, seed=2000 + n + taps)
+
+
+def test_c2_ska_n1024_sampled():
+    n, taps = 1024, 8
+    n_samples = 1 << 27
+    m_total = oracle.n_spectra(n_samples, n, taps)
+    print(f"case C2 N={n} T={taps} M={m_total}", flush=True)
+    h32 = signals.design_coeffs(n, taps, "hamming").astype(np.float32)
+    x = signals.complex_gaussian(n_samples, 1.0, seed=signals.SEED_BASE + 1)
+    got, path = run_gpu(x, h32, n, taps)
+    assert got.shape == (m_total, n)
+    pick = sample_spectra(m_total, taps)
+    ref = oracle.ppf(x, h32, n, taps, spectra=pick)
+    err = rel_err(got[pick], ref)
+    print(f"C2 path={path} sampled {len(pick)} spectra, max err / rms = {err:.3e}")
+    assert err <= TOL
+    # properties that hold at any size: finite everywhere, power as expected for white noise
+    assert np.isfinite(got).all()
+    expect = 2.0 * float(np.sum(h32.astype(np.float64) ** 2))
+    assert abs(float(np.mean(np.abs(got[::61]) ** 2)) / expect - 1.0) < 0.02
+
+
+def test_taps1_rect_is_plain_fft():
+    torch = _torch()
+    n, m_total = 512, 64
+    x = signals.complex_gaussian(m_total * n, 1.0, seed=5)
+    got, _ = run_gpu(x, np.ones(n, np.float32), n, 1)
+    want = np.fft.fft(x.astype(np.complex128).reshape(m_total, n), axis=1)
+    assert rel_err(got, want) <= TOL
+
+
+def test_impulse_reproduces_coefficients():
+    n, taps, m_total = 256, 8, 16
+    h32 = signals.design_coeffs(n, taps, "hamming").astype(np.float32)
+    t0, c0 = 10, 77
+    x = np.zeros((m_total + taps - 1) * n, np.complex64)
+    x[t0 * n + c0] = 1.0
+    got, _ = run_gpu(x, h32, n, taps)
+    for m in range(m_total):
+        mag = np.abs(got[m])
+        want = abs(float(h32[(t0 - m) * n + c0])) if t0 - taps + 1 <= m <= t0 else 0.0
+        assert np.max(np.abs(mag - want)) <= 1e-6, m
+
+
+def test_zero_spectra_is_noop_and_single_spectrum():
+    torch = _torch()
+    n, taps = 256, 4
+    h32 = signals.design_coeffs(n, taps).astype(np.float32)
+    plan = ppf.Plan(n, taps, h32)
+    x = torch.zeros((taps - 1 + 1) * n, dtype=torch.complex64, device="cuda")
+    out = torch.full((1, n), 7.0, dtype=torch.complex64, device="cuda")
+    ppf.ppf_execute(plan.handle, x, out, 0)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    xr = signals.complex_gaussian(taps * n, 1.0, seed=8)
+    got = plan.execute(torch.from_numpy(xr).cuda(), nspectra=1)
+    torch.cuda.synchronize()
+    ref = oracle.ppf(xr, h32, n, taps)
+    assert rel_err(got.cpu().numpy(), ref) <= TOL
+    plan.close()
+
+
+def test_alignment_and_overlap_errors():
+    torch = _torch()
+    n, taps = 256, 4
+    plan = ppf.Plan(n, taps, np.ones(n * taps, np.float32))
+    buf = torch.zeros(64 * n, dtype=torch.complex64, device="cuda")
+    with pytest.raises(ppf.PPFError) as ei:
+        ppf.ppf_execute(plan.handle, buf.data_ptr() + 8, torch.empty_like(buf).data_ptr(), 4)
+    assert ei.value.status == ppf.PPF_ERR_ALIGN
+    with pytest.raises(ppf.PPFError) as ei:
+        ppf.ppf_execute(plan.handle, buf, buf.data_ptr() + 16 * n * 8, 16)
+    assert ei.value.status == ppf.PPF_ERR_INVALID
+    with pytest.raises(ppf.PPFError) as ei:
+        ppf.ppf_execute(plan.handle, buf, buf, -1)
+    assert ei.value.status == ppf.PPF_ERR_INVALID
+    plan.close()
+
+
+def test_deterministic_and_paths_agree():
+    torch = _torch()
+    n, taps, m_total = 1024, 8, 1000
+    h32 = signals.design_coeffs(n, taps).astype(np.float32)
+    x = torch.from_numpy(signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=9)).cuda()
+    fused = ppf.Plan(n, taps, h32, ppf.PPF_PATH_FUSED)
+    two = ppf.Plan(n, taps, h32, ppf.PPF_PATH_TWO_PASS)
+    a = fused.execute(x).cpu().numpy()
+    b = fused.execute(x).cpu().numpy()
+    c = two.execute(x).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert rel_err(c, a.astype(np.complex128)) <= TOL
+    fused.close()
+    two.close()
