@@ -1,0 +1,235 @@
+"""Throughput benchmark of the MI355X polyphase filter bank.
+
+Default workload (one GPU): the SKA-LFAA-like single channel, N=1024
+channels, T=8 taps, 2^27 complex FP32 input samples (1 GiB), sinc x Hamming
+coefficients; a step is one ppf_execute over the whole batch (FIR presum and
+FFT of all 131065 spectra) with the input already in HBM.
+
+Prints one JSON line: input GB/s (the metric), the real-time multiple of
+the 6.5 GB/s single-channel rate (the paper's Eq. 2, streaming mode M_c),
+the roofline of the dominant kernel and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+Other workloads (--workload): c1 (N=256, T=8, 16384 spectra), sweep (the
+shape sweep N in {64, 512, 4096, 16384} x T in {4, 8, 16, 32}, one line per
+point). They print the same fields.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import pathlib
+import sys
+import time
+
+import numpy as np
+
+ROOT = pathlib.Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+from paper_1411_3656_amd import metrics, ppf, signals  # noqa: E402
+
+METRIC = "PPF input GB/s (×6.5 GB/s real-time), % HBM peak; p99 stream chunk latency"
+PROFILES = ROOT / "profiles"
+KERNEL_SOURCES = [ROOT / "paper_1411_3656_amd" / "csrc" / "ppf_kernels.hip"]
+
+WORKLOADS = {
+    "c1": dict(name="plain_n256_t8_16384spectra", N=256, T=8, window="hamming", spectra=16384, tones=True,
+               seed=signals.SEED_BASE + 0),
+    "c2": dict(name="ska_lfaa_n1024_t8_2p27", N=1024, T=8, window="hamming", samples=1 << 27, tones=False,
+               seed=signals.SEED_BASE + 1),
+}
+SWEEP_N = [64, 512, 4096, 16384]
+SWEEP_T = [4, 8, 16, 32]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary.
+
+    The summary records the kernel-source hash it was taken with; a
+    different hash means the kernel changed since, and traffic is null.
+    """
+    f = PROFILES / f"traffic_{workload}.json"
+    if not f.exists():
+        return None
+    try:
+        rec = json.loads(f.read_text())
+    except ValueError:
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, h32, budget_s: float = 12.0):
+    """FP64 oracle on a bounded sample: whole spectra of the same workload."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count() or 1
+    n, taps = cfg["N"], cfg["T"]
+    spectra = 1024
+    total_s, done = 0.0, 0
+    x = signals.complex_gaussian((spectra + taps - 1) * n, 1.0, seed=cfg["seed"] + 77)
+    oracle.ppf(x[: (16 + taps - 1) * n], h32, n, taps)            # warm the BLAS pools
+    while total_s < budget_s and done < 64:
+        t0 = time.perf_counter()
+        oracle.ppf(x, h32, n, taps)
+        total_s += time.perf_counter() - t0
+        done += 1
+    rate = done * spectra * n * 8 / total_s / 1e9
+    return {"value": round(rate, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} x {spectra} spectra of N={n}, T={taps} ({done * spectra * n} input samples), "
+                      f"{total_s:.1f} s of FP64 numpy/BLAS"}
+
+
+def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO):
+    plan = ppf.Plan(n, taps, h32, path)
+    out = torch.empty((m_total, n), dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ppf.ppf_set_stream(plan.handle, stream.cuda_stream)
+    for _ in range(warmup):
+        ppf.ppf_execute(plan.handle, x_dev, out, m_total)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        ppf.ppf_execute(plan.handle, x_dev, out, m_total)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    used_path = plan.path
+    plan.close()
+    del out
+    return ms, used_path
+
+
+def line(workload, n, taps, m_total, ms, used_path, steps, warmup, traffic=None, cpu=None):
+    in_bytes = metrics.input_bytes(n, m_total)
+    gbps = in_bytes / (ms * 1e-3) / 1e9
+    alg = metrics.algorithmic_bytes(n, taps, m_total)
+    achieved = alg / (ms * 1e-3) / 1e9
+    peak = metrics.HBM_PEAK_BYTES_PER_S / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": round(gbps, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "realtime_multiple": round(metrics.realtime_multiple(gbps * 1e9), 2),
+        "config": {"workload": workload, "N": n, "taps": taps, "nspectra": m_total,
+                   "input_samples": (m_total + taps - 1) * n,
+                   "path": {1: "fused", 2: "two_pass"}.get(used_path, str(used_path))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": peak, "unit": "GB/s",
+                     "frac": round(achieved / peak, 4),
+                     "traffic": None if traffic is None else int(traffic),
+                     "algorithmic_bytes": alg},
+    }
+    if cpu is not None:
+        rec["cpu_baseline"] = cpu
+    return rec
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "sweep", "copy"])
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        return 1
+    path = {"auto": ppf.PPF_PATH_AUTO, "fused": ppf.PPF_PATH_FUSED, "two_pass": ppf.PPF_PATH_TWO_PASS}[args.path]
+
+    if args.workload == "copy":
+        # a plain device copy of known size: the yardstick for the HBM byte
+        # counters (FETCH_SIZE, WRITE_SIZE) and the achievable copy rate
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / args.steps
+        print(json.dumps({"workload": "copy_1GiB", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "ms_per_copy": round(ms, 5), "GBps_moved": round(2 * nbytes / ms / 1e6, 1)}),
+              flush=True)
+        return 0
+
+    if args.workload == "sweep":
+        for i, n in enumerate(SWEEP_N):
+            x = signals.complex_gaussian(1 << 28, 1.0, seed=signals.SEED_BASE + 2 + 100 * i)
+            x_dev = torch.from_numpy(x).cuda()
+            del x
+            for taps in SWEEP_T:
+                h32 = signals.design_coeffs(n, taps, "hann").astype(np.float32)
+                m_total = (1 << 28) // n - taps + 1
+                ms, used = run_point(torch, n, taps, m_total, x_dev, h32, args.steps, args.warmup, path)
+                rec = line(f"sweep_n{n}_t{taps}_2p28", n, taps, m_total, ms, used, args.steps, args.warmup,
+                           measured_traffic(f"sweep_n{n}_t{taps}"))
+                print(json.dumps(rec), flush=True)
+            del x_dev
+            torch.cuda.empty_cache()
+        return 0
+
+    cfg = WORKLOADS[args.workload]
+    n, taps = cfg["N"], cfg["T"]
+    if "samples" in cfg:
+        m_total = cfg["samples"] // n - taps + 1
+    else:
+        m_total = cfg["spectra"]
+    n_samples = (m_total + taps - 1) * n
+    h32 = signals.design_coeffs(n, taps, cfg["window"]).astype(np.float32)
+    if cfg["tones"]:
+        x = signals.plain_input(n, n_samples, seed=cfg["seed"])
+    else:
+        x = signals.complex_gaussian(n_samples, 1.0, seed=cfg["seed"])
+    x_dev = torch.from_numpy(x).cuda()
+    del x
+    ms, used = run_point(torch, n, taps, m_total, x_dev, h32, args.steps, args.warmup, path)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, h32)
+    rec = line(cfg["name"], n, taps, m_total, ms, used, args.steps, args.warmup,
+               measured_traffic(args.workload), cpu)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
