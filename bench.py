@@ -95,7 +95,9 @@ def cpu_baseline(cfg, h32, budget_s: float = 12.0):
                       f"{total_s:.1f} s of FP64 numpy/BLAS"}
 
 
-def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO):
+def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO, windows=0):
+    """Average ms per execute over `steps` after `warmup`; with windows > 0
+    also the average of each of `windows` consecutive slices of the steps."""
     plan = ppf.Plan(n, taps, h32, path)
     out = torch.empty((m_total, n), dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -103,18 +105,21 @@ def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_P
     for _ in range(warmup):
         ppf.ppf_execute(plan.handle, x_dev, out, m_total)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(steps):
-        ppf.ppf_execute(plan.handle, x_dev, out, m_total)
-    end.record(stream)
+    nwin = max(1, windows)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(nwin + 1)]
+    bounds = [round(i * steps / nwin) for i in range(nwin + 1)]
+    marks[0].record(stream)
+    for w in range(nwin):
+        for _ in range(bounds[w + 1] - bounds[w]):
+            ppf.ppf_execute(plan.handle, x_dev, out, m_total)
+        marks[w + 1].record(stream)
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / steps
+    ms = marks[0].elapsed_time(marks[-1]) / steps
+    win_ms = [marks[w].elapsed_time(marks[w + 1]) / max(1, bounds[w + 1] - bounds[w]) for w in range(nwin)]
     used_path = plan.path
     plan.close()
     del out
-    return ms, used_path
+    return (ms, used_path, win_ms) if windows else (ms, used_path)
 
 
 def line(workload, n, taps, m_total, ms, used_path, steps, warmup, traffic=None, cpu=None):
@@ -153,11 +158,13 @@ def line(workload, n, taps, m_total, ms, used_path, steps, warmup, traffic=None,
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "sweep", "copy"])
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--windows", type=int, default=0,
+                    help="also report the mean step time of this many consecutive slices of the timed steps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -223,10 +230,13 @@ def main() -> int:
         x = signals.complex_gaussian(n_samples, 1.0, seed=cfg["seed"])
     x_dev = torch.from_numpy(x).cuda()
     del x
-    ms, used = run_point(torch, n, taps, m_total, x_dev, h32, args.steps, args.warmup, path)
+    res = run_point(torch, n, taps, m_total, x_dev, h32, args.steps, args.warmup, path, args.windows)
+    ms, used = res[0], res[1]
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, h32)
     rec = line(cfg["name"], n, taps, m_total, ms, used, args.steps, args.warmup,
                measured_traffic(args.workload), cpu)
+    if args.windows:
+        rec["window_ms_per_step"] = [round(w, 5) for w in res[2]]
     print(json.dumps(rec), flush=True)
     return 0
 

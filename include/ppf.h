@@ -154,6 +154,127 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
 /* ppf_destroy - wait for the plan's stream, then free the plan. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);
 
+/* ------------------------------------------------------------------------
+ * Stream form.
+ *
+ * A stream feeds an unbounded sample sequence through a plan in chunks. Its
+ * state is the last (T-1)*N input samples (the T-1 past samples of Eq. 1 per
+ * channel), kept in device memory. The outputs of successive pushes are
+ * exactly the batch PPF over zeros((T-1)*N) ++ chunk_1 ++ chunk_2 ++ ...:
+ * a chunk of S*N samples yields S spectra, whatever the chunking (the FIR
+ * depends on raw input only, section 2).
+ * ---------------------------------------------------------------------- */
+
+typedef struct ppf_stream_s* ppf_stream_t;
+
+/* One chunk: in = nspectra*N samples of the plan's input type (device),
+ * out = nspectra*N complex FP32 bins (device), 16-byte aligned, not
+ * overlapping. tag is the caller's identifier (used by the server). */
+typedef struct ppf_chunk {
+    const void* in;
+    void* out;
+    long long nspectra;
+    unsigned long long tag;
+} ppf_chunk;
+
+/* ppf_stream_create - new stream on `plan` with a zero history. The plan must
+ * outlive the stream. Allocates 2*(T-1)*N samples of device memory.
+ * Returns NULL on error. */
+ppf_stream_t ppf_stream_create(ppf_plan_t plan);
+
+/* ppf_stream_push - enqueue one chunk on the plan's HIP stream (asynchronous).
+ * Pushes to one stream are processed in order. nspectra == 0 is a no-op. */
+int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk);
+
+/* ppf_stream_get_history / ppf_stream_set_history - copy the (T-1)*N-sample
+ * history to / from host memory (synchronous: waits for the plan's stream).
+ * Saving and restoring it resumes a stream exactly (checkpoint/restore). */
+int ppf_stream_get_history(ppf_stream_t stream, void* host_dst);
+int ppf_stream_set_history(ppf_stream_t stream, const void* host_src);
+
+/* Spectra pushed so far. */
+long long ppf_stream_position(ppf_stream_t stream);
+
+/* ppf_stream_destroy - wait for the plan's stream, free the history. NULL is a no-op. */
+int ppf_stream_destroy(ppf_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Serving form.
+ *
+ * A server runs many streams of possibly different N and T on one GPU with
+ * continuous batching: chunks submitted from any host thread are grouped by
+ * a scheduler thread into batches as in-flight slots free up, the batch's
+ * work for all streams runs as one captured HIP graph (one concurrent
+ * branch per plan), and each stream's (T-1)*N-sample history stays in
+ * device memory between its chunks. Per stream the outputs equal those of
+ * the stream form (and of the batch PPF over the zero-prefixed
+ * concatenation of its chunks). Streams are admitted while their state fits
+ * the server's device-memory budget.
+ * ---------------------------------------------------------------------- */
+
+typedef struct ppf_server_s* ppf_server_t;
+
+typedef struct ppf_server_stats {
+    long long chunks_done;        /* chunks completed since the last reset */
+    long long spectra_done;
+    long long bytes_in_done;      /* input bytes of completed chunks */
+    long long batches;            /* batches launched */
+    long long admitted;           /* streams admitted (ever) */
+    long long rejected;           /* open requests refused for budget */
+    long long queued_admissions;  /* open requests that had to wait for budget */
+    long long state_bytes_used;   /* budget in use: admitted streams + server buffers */
+    double p50_us, p99_us, max_us, mean_us;  /* chunk latency: completion seen on the
+                                               host minus arrival time */
+    double elapsed_s;             /* first arrival to last completion */
+    double input_gbps;            /* bytes_in_done / elapsed_s / 1e9 */
+    double mean_batch_chunks;
+} ppf_server_stats;
+
+/* Host steady clock in nanoseconds (the time base of arrival times). */
+long long ppf_clock_ns(void);
+
+/* ppf_server_create - server with a device-memory budget in bytes for its own
+ * buffers plus stream state, and 1..4 batches in flight. Starts the
+ * scheduler thread. PPF_ERR_BUDGET if the budget cannot hold the server's
+ * own buffers (max_inflight * ~64 MiB). Returns NULL on error. */
+ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight);
+
+/* ppf_server_open_stream - open a stream on a complex-FP32 plan (at most 8
+ * distinct plans per server; plans must outlive the server). If the state
+ * does not fit the budget: PPF_ERR_BUDGET when wait_for_budget is 0, else
+ * the stream is queued and admitted, in order, when closing streams free
+ * budget; chunks may be submitted meanwhile and run once it is admitted. */
+int ppf_server_open_stream(ppf_server_t server, ppf_plan_t plan, int wait_for_budget, int* stream_id);
+
+/* 1 if the stream has been admitted, 0 if it is still waiting, <0 on error. */
+int ppf_server_stream_admitted(ppf_server_t server, int stream_id);
+
+/* ppf_server_submit - queue one chunk of a stream (thread-safe). Chunks of a
+ * stream are processed in submission order. arrival_ns is the chunk's
+ * arrival time on ppf_clock_ns (< 0: now); latency is measured from it.
+ * Device buffers must stay valid until the chunk's tag is returned by
+ * ppf_server_poll or ppf_server_drain returns. */
+int ppf_server_submit(ppf_server_t server, int stream_id, const ppf_chunk* chunk, long long arrival_ns);
+
+/* ppf_server_poll - copy up to max completed chunk tags, in completion
+ * order; returns the number copied (>= 0) or an error. */
+int ppf_server_poll(ppf_server_t server, unsigned long long* tags, int max);
+
+/* ppf_server_drain - wait until every submitted chunk has completed;
+ * PPF_ERR_BUSY after timeout_s seconds. */
+int ppf_server_drain(ppf_server_t server, double timeout_s);
+
+/* ppf_server_close_stream - no further submissions; the state is released
+ * once the stream's chunks have completed. */
+int ppf_server_close_stream(ppf_server_t server, int stream_id);
+
+int ppf_server_get_stats(ppf_server_t server, ppf_server_stats* out);
+int ppf_server_reset_stats(ppf_server_t server);
+
+/* ppf_server_destroy - finish outstanding chunks, stop the scheduler, free
+ * everything. NULL is a no-op. */
+int ppf_server_destroy(ppf_server_t server);
+
 /* Status of the most recent failure on this host thread (PPF_OK if none). */
 int ppf_last_error(void);
 /* Human-readable text of the most recent failure on this host thread. */

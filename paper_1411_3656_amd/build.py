@@ -24,7 +24,7 @@ CSRC = PKG / "csrc"
 BUILD = ROOT / "_build"
 LIB = PKG / "libppf.so"
 
-SOURCES = ["ppf_kernels.hip", "ppf_api.cpp"]
+SOURCES = ["ppf_kernels.hip", "ppf_api.cpp", "ppf_server.cpp"]
 ARCH = "gfx950"
 
 COMMON = [
@@ -42,9 +42,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP toolchain is required to build libppf.so")
 
 
-def _compile(src: str, verbose: bool) -> pathlib.Path:
-    obj = BUILD / (pathlib.Path(src).stem + ".o")
-    cmd = [hipcc(), *COMMON, "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)]
+def _compile(src: str, verbose: bool, extra=(), bdir: pathlib.Path = BUILD) -> pathlib.Path:
+    obj = bdir / (pathlib.Path(src).stem + ".o")
+    cmd = [hipcc(), *COMMON, *extra, "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)]
     if verbose:
         print(" ".join(cmd), flush=True)
     t0 = time.time()
@@ -58,28 +58,34 @@ def _compile(src: str, verbose: bool) -> pathlib.Path:
     return obj
 
 
-def build(jobs: int = 4, verbose: bool = False) -> pathlib.Path:
-    BUILD.mkdir(exist_ok=True)
+def build(jobs: int = 4, verbose: bool = False, defines=(), out: pathlib.Path | None = None) -> pathlib.Path:
+    """Compile and link; ``defines`` are extra -D flags, ``out`` another library path."""
+    lib = pathlib.Path(out) if out else LIB
+    bdir = BUILD if out is None else BUILD / lib.stem
+    bdir.mkdir(parents=True, exist_ok=True)
+    extra = [f"-D{d}" for d in defines]
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB.with_suffix(".so.tmp")
+        objs = list(ex.map(lambda s: _compile(s, verbose, extra, bdir), SOURCES))
+    tmp = lib.with_suffix(".so.tmp")
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("link of libppf.so failed")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}", flush=True)
-    return LIB
+        print(f"built {lib}", flush=True)
+    return lib
 
 
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="extra preprocessor define")
+    ap.add_argument("--out", default=None, help="library path (default: in-tree libppf.so)")
     args = ap.parse_args()
-    build(args.jobs, args.verbose)
+    build(args.jobs, args.verbose, args.defines, args.out)
 
 
 if __name__ == "__main__":

@@ -216,6 +216,13 @@ hip_fail:
 
 }  // namespace
 
+ppf::PlanDev ppf_internal_plan_dev(const ppf_plan_s* plan) { return plan->dev(); }
+
+void ppf_internal_set_error(int status, const char* message) {
+  g_status = status;
+  snprintf(g_message, sizeof g_message, "%s", message);
+}
+
 extern "C" {
 
 ppf_plan_t ppf_plan(int n_channels, int taps, const float* coeffs) {
@@ -302,6 +309,101 @@ int ppf_destroy(ppf_plan_t plan) {
   hipError_t e = hipStreamSynchronize(plan->stream);
   delete plan;
   if (e != hipSuccess) return fail_hip(e, "ppf_destroy synchronize");
+  return PPF_OK;
+}
+
+ppf_stream_t ppf_stream_create(ppf_plan_t plan) {
+  try {
+    if (!plan) { fail(PPF_ERR_INVALID, "plan is NULL"); return nullptr; }
+    ppf_stream_s* s = new (std::nothrow) ppf_stream_s;
+    if (!s) { fail(PPF_ERR_NOMEM, "host allocation"); return nullptr; }
+    s->plan = plan;
+    s->hist_samples = (long long)(plan->T - 1) * plan->N;
+    const size_t bytes = (size_t)s->hist_samples * sample_bytes(plan->in_type);
+    if (bytes > 0) {
+      for (int i = 0; i < 2; ++i) {
+        hipError_t e = hipMalloc(&s->hist[i], bytes);
+        if (e != hipSuccess) { s->hist[i] = nullptr; fail_hip(e, "stream history allocation"); delete s; return nullptr; }
+        e = hipMemset(s->hist[i], 0, bytes);
+        if (e != hipSuccess) { fail_hip(e, "stream history clear"); delete s; return nullptr; }
+      }
+    }
+    g_status = PPF_OK;
+    return s;
+  } catch (...) {
+    fail(PPF_ERR_NOMEM, "unexpected exception in ppf_stream_create");
+    return nullptr;
+  }
+}
+
+int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk) {
+  try {
+    if (!stream || !chunk) return fail(PPF_ERR_INVALID, "stream or chunk is NULL");
+    ppf_plan_t plan = stream->plan;
+    const long long S = chunk->nspectra;
+    if (S < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", S);
+    if (S == 0) { g_status = PPF_OK; return PPF_OK; }
+    if (!chunk->in || !chunk->out) return fail(PPF_ERR_INVALID, "chunk in or out is NULL");
+    if (((uintptr_t)chunk->in & 15) || ((uintptr_t)chunk->out & 15))
+      return fail(PPF_ERR_ALIGN, "chunk in and out must be 16-byte aligned");
+    const size_t sb = (size_t)sample_bytes(plan->in_type);
+    if (overlaps((uintptr_t)chunk->in, (size_t)S * plan->N * sb, (uintptr_t)chunk->out, (size_t)S * plan->N * 8))
+      return fail(PPF_ERR_INVALID, "chunk in and out overlap");
+    const long long h0 = plan->T - 1;
+    void* cur = stream->hist[stream->cur];
+    int st = run_batch(plan, cur, h0, chunk->in, chunk->out, S);
+    if (st != PPF_OK) return st;
+    if (h0 > 0) {
+      void* nxt = stream->hist[1 - stream->cur];
+      hipError_t e = ppf::launch_history(cur, chunk->in, nxt, stream->hist_samples, S * plan->N, (int)sb,
+                                         plan->stream);
+      if (e != hipSuccess) return fail_hip(e, "history kernel launch");
+      stream->cur = 1 - stream->cur;
+    }
+    stream->pushed_spectra += S;
+    g_status = PPF_OK;
+    return PPF_OK;
+  } catch (...) {
+    return fail(PPF_ERR_HIP, "unexpected exception in ppf_stream_push");
+  }
+}
+
+int ppf_stream_get_history(ppf_stream_t stream, void* host_dst) {
+  if (!stream) return fail(PPF_ERR_INVALID, "stream is NULL");
+  const size_t bytes = (size_t)stream->hist_samples * sample_bytes(stream->plan->in_type);
+  if (bytes == 0) return PPF_OK;
+  if (!host_dst) return fail(PPF_ERR_INVALID, "host_dst is NULL");
+  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  if (e != hipSuccess) return fail_hip(e, "history synchronize");
+  e = hipMemcpy(host_dst, stream->hist[stream->cur], bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "history copy");
+  g_status = PPF_OK;
+  return PPF_OK;
+}
+
+int ppf_stream_set_history(ppf_stream_t stream, const void* host_src) {
+  if (!stream) return fail(PPF_ERR_INVALID, "stream is NULL");
+  const size_t bytes = (size_t)stream->hist_samples * sample_bytes(stream->plan->in_type);
+  if (bytes == 0) return PPF_OK;
+  if (!host_src) return fail(PPF_ERR_INVALID, "host_src is NULL");
+  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  if (e != hipSuccess) return fail_hip(e, "history synchronize");
+  e = hipMemcpy(stream->hist[stream->cur], host_src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail_hip(e, "history copy");
+  g_status = PPF_OK;
+  return PPF_OK;
+}
+
+long long ppf_stream_position(ppf_stream_t stream) {
+  if (!stream) { fail(PPF_ERR_INVALID, "stream is NULL"); return -1; }
+  return stream->pushed_spectra;
+}
+
+int ppf_stream_destroy(ppf_stream_t stream) {
+  if (!stream) return PPF_OK;
+  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  delete stream;
+  if (e != hipSuccess) return fail_hip(e, "ppf_stream_destroy synchronize");
   return PPF_OK;
 }
 

@@ -30,6 +30,31 @@ struct PlanDev {
   const void* tw;      // N complex FP32 twiddles exp(-2 pi i k/N)
 };
 
+// Descriptor tables of the serving form (device memory, filled by the host).
+// A tile is a run of spectra whose input is x0 (h0 blocks) ++ x1 and whose
+// spectrum m goes to out + m*N.
+struct TileDesc {
+  const void* x0;
+  const void* x1;
+  void* out;
+  int h0;
+  int count;
+};
+// The tiles of one kernel class are tiles[first .. first+ntiles).
+struct DescClass {
+  int first;
+  int ntiles;
+};
+// History update: dst = last hs samples of (a ++ b); a holds the hs samples
+// before b, b holds cs samples (complex FP32).
+struct HistDesc {
+  const void* a;
+  const void* b;
+  void* dst;
+  int hs;
+  int cs;
+};
+
 int taps_template(int T);                       // smallest supported TP >= T, 0 if none
 bool fused_available(int N, int TP);
 bool fft_available(int N);
@@ -41,6 +66,17 @@ hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
 hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
 // Batched N-point FFT of M contiguous blocks (in x1) to a.out.
 hipError_t launch_fft(const PlanDev& pd, const void* in, void* out, long long M, hipStream_t st);
+// Descriptor launches with persistent grids sized for at most max_tiles
+// tiles (max_entries history entries); the counts are read on the device.
+hipError_t launch_fused_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                             hipStream_t st);
+hipError_t launch_fft_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                           hipStream_t st);
+hipError_t launch_fir_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                           hipStream_t st);
+hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, hipStream_t st);
+// One-time set-up of a plan's descriptor launchers, to run before capture.
+hipError_t prepare_desc(const PlanDev& pd, bool fused);
 // FP64 twiddle generation: tw[k] = exp(-2 pi i k/N) rounded to FP32.
 hipError_t launch_twiddles(void* tw, int N, hipStream_t st);
 // Stream history update: new = last `hist_samples` samples of (old ++ chunk).
@@ -49,3 +85,9 @@ hipError_t launch_history(const void* old_hist, const void* chunk, void* new_his
                           hipStream_t st);
 
 }  // namespace ppf
+
+// Plan internals for the server (implemented beside the plan object).
+struct ppf_plan_s;
+ppf::PlanDev ppf_internal_plan_dev(const ppf_plan_s* plan);
+// Record a failure as the calling thread's last error.
+void ppf_internal_set_error(int status, const char* message);

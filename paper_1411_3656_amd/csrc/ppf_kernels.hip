@@ -18,7 +18,7 @@
 // blocks are loads already in flight for later spectra. The ring index of a
 // block is static because the spectrum loop is unrolled by the ring size.
 // Between Stockham stages the group exchanges data through LDS (split
-// re/im planes, padded one word per 32 to spread banks, double-buffered
+// re/im planes, swizzled or padded to spread banks, double-buffered
 // when it fits so that one barrier per exchange suffices). Twiddles per
 // thread are constant across spectra and are loaded into registers once.
 //
@@ -180,10 +180,25 @@ constexpr int tw_offset(int N, int R, int RX, int s) {
 }
 constexpr int tw_total(int N, int R, int RX) { return tw_offset(N, R, RX, num_stages(N, RX)); }
 
-// LDS plane: N floats padded one word per 32, rounded so that groups that
-// share a wave start on distinct bank offsets.
-__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
+// LDS word address of element i of a plane. gfx950 LDS has 64 four-byte
+// banks serving a whole wave per access. For N >= 256 (one group per wave)
+// element i goes to i XOR a mask of its 64-word row that spreads the row
+// index over bits 0-5 (row ^ row<<2 ^ row<<4): contiguous reads stay one
+// row, and the strided Stockham writes, whose lanes fall in rows with
+// different low row bits but fixed low offset bits, land in distinct banks.
+// Smaller N (several groups per wave) pad one word per 32 and shift group
+// planes by W words.
+template <int N>
+__device__ __forceinline__ int lds_index(int i) {
+  if constexpr (N >= 256) {
+    const int row = i >> 6;
+    return i ^ ((row ^ (row << 2) ^ (row << 4)) & 63);
+  } else {
+    return i + (i >> 5);
+  }
+}
 constexpr int plane_floats(int N, int W) {
+  if (N >= 256) return N;
   const int p = N + N / 32;
   return W < 32 ? ((p + 31) / 32) * 32 + W : p;
 }
@@ -192,14 +207,16 @@ constexpr int plane_floats(int N, int W) {
 // Per-group FFT through LDS
 // --------------------------------------------------------------------------
 
-template <int N, int R, int RX, int G, bool DB, bool TWG>
+// B spectra go through the stages together: they share every barrier and
+// twiddle, and give each wave independent work between barriers.
+template <int N, int R, int RX, int G, int B, bool DB, bool TWG>
 struct GroupFft {
   static constexpr int W = N / R;
   static constexpr int L = num_stages(N, RX);
   static constexpr int PL = plane_floats(N, W);      // floats per plane
   static constexpr int NBUF = DB ? 2 : 1;
   static constexpr int NTW = TWG ? 1 : (tw_total(N, R, RX) > 0 ? tw_total(N, R, RX) : 1);
-  static constexpr size_t lds_bytes() { return size_t(NBUF) * 2 * G * PL * sizeof(float); }
+  static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
 
   float* lds;      // shared memory base of the block
   int grp, j;
@@ -207,8 +224,8 @@ struct GroupFft {
   const v2f* tw;   // twiddle table (global)
   v2f twr[NTW];
 
-  __device__ __forceinline__ float* plane(int buf, int reim) const {
-    return lds + ((buf * 2 + reim) * G + grp) * PL;
+  __device__ __forceinline__ float* plane(int buf, int b, int reim) const {
+    return lds + (((buf * B + b) * 2 + reim) * G + grp) * PL;
   }
 
   template <int S>
@@ -248,53 +265,65 @@ struct GroupFft {
   }
 
   template <int S>
-  __device__ __forceinline__ void stage(v2f (&v)[R]) {
+  __device__ __forceinline__ void stage(v2f (&v)[B][R]) {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     constexpr int nb = R / r;
     if constexpr (S > 0) {
-      const int b = DB ? par : 0;
-      const float* re = plane(b, 0);
-      const float* im = plane(b, 1);
+      const int buf = DB ? par : 0;
 #pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const int idx = pad32(j + e * W);
-        v[e].x = re[idx];
-        v[e].y = im[idx];
+      for (int b = 0; b < B; ++b) {
+        const float* re = plane(buf, b, 0);
+        const float* im = plane(buf, b, 1);
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const int idx = lds_index<N>(j + e * W);
+          v[b][e].x = re[idx];
+          v[b][e].y = im[idx];
+        }
       }
       if constexpr (DB) par ^= 1;
 #pragma unroll
       for (int i = 0; i < nb; ++i)
 #pragma unroll
-        for (int q = 1; q < r; ++q) v[i + q * nb] = cmul(v[i + q * nb], twiddle<S>(i, q));
+        for (int q = 1; q < r; ++q) {
+          const v2f w = twiddle<S>(i, q);
+#pragma unroll
+          for (int b = 0; b < B; ++b) v[b][i + q * nb] = cmul(v[b][i + q * nb], w);
+        }
     }
     if constexpr (S == L - 1) {
 #pragma unroll
-      for (int i = 0; i < nb; ++i) {
-        v2f t[r];
+      for (int b = 0; b < B; ++b)
 #pragma unroll
-        for (int q = 0; q < r; ++q) t[q] = v[i + q * nb];
-        dft<r>(t);
+        for (int i = 0; i < nb; ++i) {
+          v2f t[r];
 #pragma unroll
-        for (int q = 0; q < r; ++q) v[i + q * nb] = t[q];
-      }
+          for (int q = 0; q < r; ++q) t[q] = v[b][i + q * nb];
+          dft<r>(t);
+#pragma unroll
+          for (int q = 0; q < r; ++q) v[b][i + q * nb] = t[q];
+        }
     } else {
       if constexpr (!DB) __syncthreads();   // earlier reads of the single buffer are done
-      const int b = DB ? par : 0;
-      float* re = plane(b, 0);
-      float* im = plane(b, 1);
+      const int buf = DB ? par : 0;
 #pragma unroll
-      for (int i = 0; i < nb; ++i) {
-        v2f t[r];
+      for (int b = 0; b < B; ++b) {
+        float* re = plane(buf, b, 0);
+        float* im = plane(buf, b, 1);
 #pragma unroll
-        for (int q = 0; q < r; ++q) t[q] = v[i + q * nb];
-        dft<r>(t);
-        const int bf = j + i * W;
-        const int base = (bf / Ns) * Ns * r + (bf % Ns);
+        for (int i = 0; i < nb; ++i) {
+          v2f t[r];
 #pragma unroll
-        for (int q = 0; q < r; ++q) {
-          const int idx = pad32(base + q * Ns);
-          re[idx] = t[q].x;
-          im[idx] = t[q].y;
+          for (int q = 0; q < r; ++q) t[q] = v[b][i + q * nb];
+          dft<r>(t);
+          const int bf = j + i * W;
+          const int base = (bf / Ns) * Ns * r + (bf % Ns);
+#pragma unroll
+          for (int q = 0; q < r; ++q) {
+            const int idx = lds_index<N>(base + q * Ns);
+            re[idx] = t[q].x;
+            im[idx] = t[q].y;
+          }
         }
       }
       __syncthreads();
@@ -302,15 +331,15 @@ struct GroupFft {
   }
 
   template <int S>
-  __device__ __forceinline__ void run_from(v2f (&v)[R]) {
+  __device__ __forceinline__ void run_from(v2f (&v)[B][R]) {
     if constexpr (S < L) {
       stage<S>(v);
       run_from<S + 1>(v);
     }
   }
 
-  // in: v[e] = u[j + e*W]; out: v[e] = X[j + e*W]
-  __device__ __forceinline__ void run(v2f (&v)[R]) { run_from<0>(v); }
+  // in: v[b][e] = u_b[j + e*W]; out: v[b][e] = X_b[j + e*W]
+  __device__ __forceinline__ void run(v2f (&v)[B][R]) { run_from<0>(v); }
 };
 
 // --------------------------------------------------------------------------
@@ -329,98 +358,216 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // fused FIR + FFT kernel
 // --------------------------------------------------------------------------
 
+// Input blocks are streamed with non-temporal loads unless disabled at
+// build time (measured faster on MI355X for the one-pass batch).
+#ifndef PPF_NT_LOADS
+#define PPF_NT_LOADS 1
+#endif
+constexpr bool kNtLoads = PPF_NT_LOADS != 0;
+
+// Block and spectrum indices of one launch fit in 32 bits (the host splits
+// larger batches), so their arithmetic and compares stay on the scalar unit.
 struct FusedParams {
   const v2f* x0;       // first input segment (h0 blocks)
   const v2f* x1;       // second input segment
-  long long h0;
   v2f* out;
   const float* coef;   // TP*N
   const v2f* tw;       // N twiddles
-  long long M;         // spectra
+  int h0;
+  int M;               // spectra
   int S;               // spectra per group tile
   int d;               // leading zero tap segments (TP - T)
   int nblocks;
 };
 
+// One tile of spectra: the input is the concatenation x0 (h0 blocks) ++ x1,
+// spectrum m of the tile reads blocks m .. m+T-1 of it and is written to
+// out + m*N.
+struct TileArgs {
+  const v2f* x0;
+  const v2f* x1;
+  v2f* out;
+  int h0;
+};
+
 template <int N>
-__device__ __forceinline__ const v2f* block_ptr(const FusedParams& p, long long rb) {
-  return rb < p.h0 ? p.x0 + rb * N : p.x1 + (rb - p.h0) * N;
+__device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
+  return rb < a.h0 ? a.x0 + (long long)rb * N : a.x1 + (long long)(rb - a.h0) * N;
 }
 
-template <int N, int R, int RX, int G, int TP, int PF, bool DB, bool TWG>
+// Per-block engine of the fused kernel: coefficients, twiddles and lane
+// offsets are loaded once and reused by every tile the block processes.
+//
+// Ring of Q = TP + PF blocks; slot s always holds a block whose index is
+// s modulo Q (counted from the tile start). B spectra are computed per
+// step; the B blocks loaded at a step replace the B oldest, which no later
+// spectrum needs, so any Q >= TP + B - 1 is hazard-free and PF - B + 1
+// blocks of each step are loads running ahead.
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
+struct FusedEngine {
+  static constexpr int W = N / R;
+  static constexpr int Q = TP + PF;
+  static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
+  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
+
+  Fft fft;
+  int j;
+  int d;
+  float hreg[TP][R];
+  uint32_t loff[R];    // byte offset of this thread's channels inside a block
+
+  __device__ __forceinline__ void init(float* smem, int grp, int j_, const float* coef, const v2f* tw, int d_) {
+    j = j_;
+    d = d_;
+    fft.init(smem, grp, j, tw);
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int e = 0; e < R; ++e) hreg[t][e] = coef[t * N + j + e * W];
+#pragma unroll
+    for (int e = 0; e < R; ++e) loff[e] = (uint32_t)(j + e * W) * (uint32_t)sizeof(v2f);
+  }
+
+  // Spectra m0 .. m0+ng-1 of the tile; niter >= ng is the same for every
+  // group of the block (barriers), extra steps compute but store nothing.
+  __device__ __forceinline__ void run(const TileArgs& a, int m0, int ng, int niter) {
+    // virtual blocks this group reads: [vb_lo, vb_hi). Below vb_lo the taps
+    // are the zero padding; at or above vb_hi only spectra beyond the tile
+    // would use them. Those slots are not loaded.
+    const int vb_lo = m0 > d ? m0 : d;
+    const int vb_hi = ng > 0 ? m0 + ng + TP - 1 : m0;
+
+    // zero start: a slot that is never loaded holds a finite value, so a
+    // zero padding tap times it is exactly zero
+    v2f ring[Q][R];
+#pragma unroll
+    for (int s = 0; s < Q; ++s)
+#pragma unroll
+      for (int e = 0; e < R; ++e) { ring[s][e].x = 0.f; ring[s][e].y = 0.f; }
+    auto load = [&](v2f (&dst)[R], int vb) {
+      if (vb >= vb_lo && vb < vb_hi) {
+        if constexpr (G == 1) {
+          const char* bp = (const char*)block_ptr<N>(a, vb - d);
+#pragma unroll
+          for (int e = 0; e < R; ++e) {
+            if constexpr (kNtLoads) dst[e] = __builtin_nontemporal_load((const v2f*)(bp + loff[e]));
+            else dst[e] = *(const v2f*)(bp + loff[e]);
+          }
+        } else {
+          const v2f* src = block_ptr<N>(a, vb - d) + j;
+#pragma unroll
+          for (int e = 0; e < R; ++e) dst[e] = src[e * W];
+        }
+      }
+    };
+
+#pragma unroll
+    for (int s = 0; s < Q - B; ++s) load(ring[s], m0 + s);
+
+    for (int base = 0; base < niter; base += Q) {
+#pragma unroll
+      for (int k = 0; k < Q; k += B) {
+        const int it = base + k;
+        if (it >= niter) break;
+#pragma unroll
+        for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
+        v2f v[B][R];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+          for (int e = 0; e < R; ++e) {
+            v2f acc;
+            acc.x = hreg[0][e] * ring[(k + b) % Q][e].x;
+            acc.y = hreg[0][e] * ring[(k + b) % Q][e].y;
+#pragma unroll
+            for (int t = 1; t < TP; ++t) {
+              acc.x = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].x, acc.x);
+              acc.y = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].y, acc.y);
+            }
+            v[b][e] = acc;
+          }
+        fft.run(v);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (it + b < ng) {
+            if constexpr (G == 1) {
+              char* ob = (char*)(a.out + (long long)(m0 + it + b) * N);
+#pragma unroll
+              for (int e = 0; e < R; ++e) __builtin_nontemporal_store(v[b][e], (v2f*)(ob + loff[e]));
+            } else {
+              v2f* dst = a.out + (long long)(m0 + it + b) * N + j;
+#pragma unroll
+              for (int e = 0; e < R; ++e) __builtin_nontemporal_store(v[b][e], dst + e * W);
+            }
+          }
+        }
+      }
+    }
+  }
+};
+
+// Batch form: a wave of tiles of S consecutive spectra covers the batch;
+// group g of block lb owns the tile (lb*G + g).
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
 __global__ void __launch_bounds__((N / R) * G)
 ppf_fused_kernel(FusedParams p) {
   constexpr int W = N / R;
-  constexpr int Q = TP + PF;
-  using Fft = GroupFft<N, R, RX, G, DB, TWG>;
   extern __shared__ float smem[];
-
   const int tid = threadIdx.x;
   const int grp = (G == 1) ? 0 : tid / W;
   const int j = (G == 1) ? tid : tid % W;
   const int lb = xcd_remap(blockIdx.x, p.nblocks);
-  const long long blk_m0 = (long long)lb * G * p.S;
+  const int blk_m0 = lb * G * p.S;
   if (blk_m0 >= p.M) return;                                   // whole block idle
-  const long long m0 = blk_m0 + (long long)grp * p.S;
-  const long long rem = p.M - m0;
-  const int ng = rem <= 0 ? 0 : (rem < p.S ? (int)rem : p.S);  // this group's spectra
-  const long long brem = p.M - blk_m0;
-  const int niter = brem < p.S ? (int)brem : p.S;              // uniform over the block
-  // virtual blocks this group reads: [m0, vb_end); none for an idle group
-  const long long vb_end = ng > 0 ? m0 + ng + TP - 1 : m0;
+  const int m0 = blk_m0 + grp * p.S;
+  const int rem = p.M - m0;
+  const int ng = rem <= 0 ? 0 : (rem < p.S ? rem : p.S);       // this group's spectra
+  const int brem = p.M - blk_m0;
+  const int niter = brem < p.S ? brem : p.S;                   // uniform over the block
 
-  Fft fft;
-  fft.init(smem, grp, j, p.tw);
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG> eng;
+  eng.init(smem, grp, j, p.coef, p.tw, p.d);
+  TileArgs a{p.x0, p.x1, p.out, p.h0};
+  eng.run(a, m0, ng, niter);
+}
 
-  float hreg[TP][R];
-#pragma unroll
-  for (int t = 0; t < TP; ++t)
-#pragma unroll
-    for (int e = 0; e < R; ++e) hreg[t][e] = p.coef[t * N + j + e * W];
+// Descriptor form (serving): the tiles are listed in device memory; a
+// persistent grid walks them, G tiles per block at a time. Every wave of a
+// block exits at the same tile index, after the same number of barriers.
 
-  v2f ring[Q][R];
-  auto load = [&](v2f (&dst)[R], long long vb) {
-    const long long rb = vb - p.d;
-    if (vb < vb_end && rb >= 0) {
-      const v2f* src = block_ptr<N>(p, rb) + j;
-#pragma unroll
-      for (int e = 0; e < R; ++e) dst[e] = src[e * W];
-    } else {
-#pragma unroll
-      for (int e = 0; e < R; ++e) { dst[e].x = 0.f; dst[e].y = 0.f; }
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
+__global__ void __launch_bounds__((N / R) * G)
+ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, const v2f* tw, int d) {
+  constexpr int W = N / R;
+  extern __shared__ float smem[];
+  __shared__ int s_count[G];
+  const int tid = threadIdx.x;
+  const int grp = (G == 1) ? 0 : tid / W;
+  const int j = (G == 1) ? tid : tid % W;
+  const int first = cls->first;
+  const int ntiles = cls->ntiles;
+  if ((int)blockIdx.x * G >= ntiles) return;                  // whole block idle
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG> eng;
+  eng.init(smem, grp, j, coef, tw, d);
+  for (int t0 = blockIdx.x * G; t0 < ntiles; t0 += gridDim.x * G) {
+    const int t = t0 + grp;
+    TileArgs a{nullptr, nullptr, nullptr, 0};
+    int count = 0;
+    if (t < ntiles) {
+      const TileDesc& td = tiles[first + t];
+      a = TileArgs{(const v2f*)td.x0, (const v2f*)td.x1, (v2f*)td.out, td.h0};
+      count = td.count;
     }
-  };
-
+    int niter = count;
+    if constexpr (G > 1) {
+      if (j == 0) s_count[grp] = count;
+      __syncthreads();
+      niter = 0;
 #pragma unroll
-  for (int s = 0; s < Q - 1; ++s) load(ring[s], m0 + s);
-
-  v2f* outg = p.out + m0 * N + j;
-  for (int base = 0; base < niter; base += Q) {
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const int it = base + k;
-      if (it >= niter) break;
-      load(ring[(k + Q - 1) % Q], m0 + it + Q - 1);
-      v2f v[R];
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        v2f a;
-        a.x = hreg[0][e] * ring[k % Q][e].x;
-        a.y = hreg[0][e] * ring[k % Q][e].y;
-#pragma unroll
-        for (int t = 1; t < TP; ++t) {
-          a.x = fmaf(hreg[t][e], ring[(k + t) % Q][e].x, a.x);
-          a.y = fmaf(hreg[t][e], ring[(k + t) % Q][e].y, a.y);
-        }
-        v[e] = a;
-      }
-      fft.run(v);
-      if (it < ng) {
-        v2f* dst = outg + (long long)it * N;
-#pragma unroll
-        for (int e = 0; e < R; ++e) __builtin_nontemporal_store(v[e], dst + e * W);
-      }
+      for (int g = 0; g < G; ++g) niter = s_count[g] > niter ? s_count[g] : niter;
+      __syncthreads();
     }
+    eng.run(a, 0, count, niter);
   }
 }
 
@@ -431,14 +578,13 @@ ppf_fused_kernel(FusedParams p) {
 struct FirParams {
   const v2f* x0;
   const v2f* x1;
-  long long h0;
   v2f* out;            // u, M*N
   const float* coef;   // TP*N
-  long long M;
+  int h0;
+  int M;
   int N;
   int S;
   int d;
-  int pad_;
 };
 
 template <int TP, int PF>
@@ -446,29 +592,31 @@ __global__ void __launch_bounds__(256) ppf_fir_kernel(FirParams p) {
   constexpr int Q = TP + PF;
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
   const int c = (int)(g & (p.N - 1));
-  const long long m0 = (g / p.N) * p.S;
-  if (m0 >= p.M) return;
-  const long long rem = p.M - m0;
-  const int ng = rem < p.S ? (int)rem : p.S;
-  const long long vb_end = m0 + ng + TP - 1;
+  const long long tile = g / p.N;
+  if (tile * p.S >= p.M) return;
+  const int m0 = (int)tile * p.S;
+  const int rem = p.M - m0;
+  const int ng = rem < p.S ? rem : p.S;
+  const int vb_lo = m0 > p.d ? m0 : p.d;
+  const int vb_hi = m0 + ng + TP - 1;
 
   float hreg[TP];
 #pragma unroll
   for (int t = 0; t < TP; ++t) hreg[t] = p.coef[(long long)t * p.N + c];
 
   v2f ring[Q];
-  auto load = [&](v2f& dst, long long vb) {
-    const long long rb = vb - p.d;
-    if (vb < vb_end && rb >= 0) {
-      dst = rb < p.h0 ? p.x0[rb * p.N + c] : p.x1[(rb - p.h0) * p.N + c];
-    } else {
-      dst.x = 0.f; dst.y = 0.f;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) { ring[s].x = 0.f; ring[s].y = 0.f; }
+  auto load = [&](v2f& dst, int vb) {
+    if (vb >= vb_lo && vb < vb_hi) {
+      const int rb = vb - p.d;
+      dst = rb < p.h0 ? p.x0[(long long)rb * p.N + c] : p.x1[(long long)(rb - p.h0) * p.N + c];
     }
   };
 #pragma unroll
   for (int s = 0; s < Q - 1; ++s) load(ring[s], m0 + s);
 
-  v2f* outg = p.out + m0 * p.N + c;
+  v2f* outg = p.out + (long long)m0 * p.N + c;
   for (int base = 0; base < ng; base += Q) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -484,6 +632,56 @@ __global__ void __launch_bounds__(256) ppf_fir_kernel(FirParams p) {
         a.y = fmaf(hreg[t], ring[(k + t) % Q].y, a.y);
       }
       outg[(long long)it * p.N] = a;
+    }
+  }
+}
+
+// Descriptor form of the FIR pass (serving): work item w of the persistent
+// grid is channel w % N of tile w / N; the tile's out is its workspace.
+template <int TP, int PF>
+__global__ void __launch_bounds__(256)
+ppf_fir_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, int N, int d) {
+  constexpr int Q = TP + PF;
+  const int first = cls->first;
+  const long long items = (long long)cls->ntiles * N;
+  for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < items; w += (long long)gridDim.x * 256) {
+    const int t = (int)(w / N);
+    const int c = (int)(w - (long long)t * N);
+    const TileDesc& td = tiles[first + t];
+    const int ng = td.count;
+    const int vb_lo = d;
+    const int vb_hi = ng + TP - 1;
+    float hreg[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) hreg[k] = coef[(long long)k * N + c];
+    v2f ring[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) { ring[s].x = 0.f; ring[s].y = 0.f; }
+    auto load = [&](v2f& dst, int vb) {
+      if (vb >= vb_lo && vb < vb_hi) {
+        const int rb = vb - d;
+        dst = rb < td.h0 ? ((const v2f*)td.x0)[(long long)rb * N + c] : ((const v2f*)td.x1)[(long long)(rb - td.h0) * N + c];
+      }
+    };
+#pragma unroll
+    for (int s = 0; s < Q - 1; ++s) load(ring[s], s);
+    v2f* outg = (v2f*)td.out + c;
+    for (int base = 0; base < ng; base += Q) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int it = base + k;
+        if (it >= ng) break;
+        load(ring[(k + Q - 1) % Q], it + Q - 1);
+        v2f acc;
+        acc.x = hreg[0] * ring[k % Q].x;
+        acc.y = hreg[0] * ring[k % Q].y;
+#pragma unroll
+        for (int tt = 1; tt < TP; ++tt) {
+          acc.x = fmaf(hreg[tt], ring[(k + tt) % Q].x, acc.x);
+          acc.y = fmaf(hreg[tt], ring[(k + tt) % Q].y, acc.y);
+        }
+        outg[(long long)it * N] = acc;
+      }
     }
   }
 }
@@ -510,9 +708,30 @@ __global__ void ppf_history_kernel(const E* old_h, const E* chunk, E* new_h, lon
   if (i < hs) new_h[i] = (i + cs < hs) ? old_h[i + cs] : chunk[i + cs - hs];
 }
 
+// Descriptor form: entry e writes the last hs samples of (a ++ b) to dst,
+// a holding the hs samples before b and b holding cs samples.
+__global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count, const HistDesc* h) {
+  const int n = *count;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const HistDesc hd = h[e];
+    const v2f* a = (const v2f*)hd.a;
+    const v2f* b = (const v2f*)hd.b;
+    v2f* dst = (v2f*)hd.dst;
+    for (int i = threadIdx.x; i < hd.hs; i += 256) {
+      const long long k = (long long)i + hd.cs;
+      dst[i] = k < hd.hs ? a[k] : b[k - hd.hs];
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // configurations and dispatch
 // --------------------------------------------------------------------------
+
+// Build-time override of the prefetch depth of the fused kernels (tuning).
+#ifndef PPF_PF_FUSED_OVERRIDE
+#define PPF_PF_FUSED_OVERRIDE 0
+#endif
 
 // elements per thread R and groups per block G for the FFT of N points
 constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : (N <= 8192 ? 16 : 32)); }
@@ -520,11 +739,23 @@ constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
 constexpr int cfg_W(int N) { return N / cfg_R(N); }
 constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
 constexpr int cfg_PF(int N, int TP) {
-  return TP == 1 ? (N >= 16384 ? 0 : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3))) : (N >= 2048 ? 2 : 4);
+  return TP == 1 ? (N >= 16384 ? 0 : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
+                 : (N >= 2048 ? 2 : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
 }
 constexpr bool cfg_TWG(int N) { return N >= 16384; }
-constexpr bool cfg_DB(int N) {
-  return 2ull * 2 * cfg_G(N) * plane_floats(N, cfg_W(N)) * sizeof(float) <= 80 * 1024;
+// spectra per FFT pass (build-time tuning; 4 measured best at N=1024, T=8)
+#ifndef PPF_BATCH_OVERRIDE
+#define PPF_BATCH_OVERRIDE 4
+#endif
+constexpr bool batch_fits(int N, int TP, int B) {
+  return (TP + cfg_PF(N, TP)) % B == 0 && TP + cfg_PF(N, TP) >= TP + B - 1;
+}
+constexpr int cfg_B(int N, int TP) {
+  // with 16 taps the ring already fills the register file
+  return PPF_BATCH_OVERRIDE > 1 && TP <= 8 && batch_fits(N, TP, PPF_BATCH_OVERRIDE) ? PPF_BATCH_OVERRIDE : 1;
+}
+constexpr bool cfg_DB(int N, int B) {
+  return 2ull * B * 2 * cfg_G(N) * plane_floats(N, cfg_W(N)) * sizeof(float) <= 80 * 1024;
 }
 
 struct KernelInfo {
@@ -553,42 +784,72 @@ static int occupancy(const KernelInfo& ki) {
 
 template <int N, int TP>
 static const KernelInfo& fused_info() {
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP);
-  constexpr bool DB = cfg_DB(N), TWG = cfg_TWG(N);
-  using Fft = GroupFft<N, R, RX, G, DB, TWG>;
-  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, TP, PF, DB, TWG>,
+  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
+  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
+  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG>,
                              (N / R) * G, G, Fft::lds_bytes()};
   return ki;
 }
 
+// Largest number of spectra in one launch: block and spectrum indices stay
+// below 2^31 inside the kernels.
+constexpr long long kMaxLaunchSpectra = 1ll << 28;
+
+// Part [s0, s0+k) of a batch: the concatenated input starts at block s0.
+static BatchArgs sub_batch(const BatchArgs& a, int N, size_t sample_bytes, long long s0, long long k) {
+  BatchArgs o;
+  if (s0 < a.h0) {
+    o.x0 = (const char*)a.x0 + (size_t)s0 * N * sample_bytes;
+    o.h0 = a.h0 - s0;
+    o.x1 = a.x1;
+  } else {
+    o.x0 = a.x1;
+    o.h0 = 0;
+    o.x1 = (const char*)a.x1 + (size_t)(s0 - a.h0) * N * sample_bytes;
+  }
+  o.out = (char*)a.out + (size_t)s0 * N * 8;
+  o.M = k;
+  return o;
+}
+
 template <int N, int TP>
-static hipError_t fused_launch(const PlanDev& pd, const BatchArgs& a, const float* coef, int T, hipStream_t st) {
+static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const float* coef, int T,
+                                   hipStream_t st) {
   const KernelInfo& ki = fused_info<N, TP>();
   static const int occ = occupancy(ki);
   const long long resident_groups = (long long)device_cus() * occ * ki.G;
   long long S = (a.M + resident_groups - 1) / resident_groups;
   if (S < 2 * TP) S = 2 * TP;                                  // bound the tap-window re-reads
-  if (S > (1 << 30)) S = 1 << 30;
   const long long groups = (a.M + S - 1) / S;
   const long long nblocks = (groups + ki.G - 1) / ki.G;
   if (nblocks <= 0) return hipSuccess;
-  if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
   FusedParams p;
   p.x0 = (const v2f*)a.x0;
   p.x1 = (const v2f*)a.x1;
-  p.h0 = a.h0;
   p.out = (v2f*)a.out;
   p.coef = coef;
   p.tw = (const v2f*)pd.tw;
-  p.M = a.M;
+  p.h0 = (int)a.h0;
+  p.M = (int)a.M;
   p.S = (int)S;
   p.d = TP - T;
   p.nblocks = (int)nblocks;
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP);
-  constexpr bool DB = cfg_DB(N), TWG = cfg_TWG(N);
-  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, TP, PF, DB, TWG>), dim3((unsigned)nblocks), dim3(ki.block),
+  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
+  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG>), dim3((unsigned)nblocks), dim3(ki.block),
                      ki.lds, st, p);
   return hipGetLastError();
+}
+
+template <int N, int TP>
+static hipError_t fused_launch(const PlanDev& pd, const BatchArgs& a, const float* coef, int T, hipStream_t st) {
+  for (long long s0 = 0; s0 < a.M; s0 += kMaxLaunchSpectra) {
+    const long long k = a.M - s0 < kMaxLaunchSpectra ? a.M - s0 : kMaxLaunchSpectra;
+    const hipError_t e = fused_launch_one<N, TP>(pd, sub_batch(a, N, 8, s0, k), coef, T, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 typedef hipError_t (*FusedFn)(const PlanDev&, const BatchArgs&, const float*, int, hipStream_t);
@@ -671,17 +932,17 @@ static hipError_t fir_launch(const PlanDev& pd, const BatchArgs& a, hipStream_t 
   const long long nblocks = (threads + 255) / 256;
   if (nblocks <= 0) return hipSuccess;
   if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (a.M > kMaxLaunchSpectra || a.h0 > kMaxLaunchSpectra) return hipErrorInvalidValue;
   FirParams p;
   p.x0 = (const v2f*)a.x0;
   p.x1 = (const v2f*)a.x1;
-  p.h0 = a.h0;
   p.out = (v2f*)a.out;
   p.coef = pd.coef;
-  p.M = a.M;
+  p.h0 = (int)a.h0;
+  p.M = (int)a.M;
   p.N = pd.N;
   p.S = (int)S;
   p.d = TP - pd.T;
-  p.pad_ = 0;
   hipLaunchKernelGGL((ppf_fir_kernel<TP, PF>), dim3((unsigned)nblocks), dim3(256), 0, st, p);
   return hipGetLastError();
 }
@@ -701,6 +962,127 @@ hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
     case 64: return fir_launch<64>(pd, a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---- descriptor launchers (persistent grids, fixed across graph replays)
+
+template <int N, int TP>
+static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                                    const float* coef, int T, hipStream_t st) {
+  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
+  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
+  auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG>;
+  static const int occ = [&] {
+    KernelInfo ki{(const void*)kern, (N / R) * G, G, Fft::lds_bytes()};
+    return occupancy(ki);
+  }();
+  if (!cls) return hipSuccess;                 // warm-up call: occupancy only
+  long long grid = (long long)device_cus() * occ;
+  const long long need = (max_tiles + G - 1) / G;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((N / R) * G), Fft::lds_bytes(), st, cls, tiles, coef,
+                     (const v2f*)pd.tw, TP - T);
+  return hipGetLastError();
+}
+
+typedef hipError_t (*FusedDescFn)(const PlanDev&, const DescClass*, const TileDesc*, int, const float*, int,
+                                  hipStream_t);
+
+template <int N>
+static FusedDescFn fused_desc_for_taps(int TP) {
+  switch (TP) {
+    case 1: return &fused_desc_launch<N, 1>;
+    case 2: if constexpr (fused_ok(N, 2)) return &fused_desc_launch<N, 2>; else return nullptr;
+    case 4: if constexpr (fused_ok(N, 4)) return &fused_desc_launch<N, 4>; else return nullptr;
+    case 8: if constexpr (fused_ok(N, 8)) return &fused_desc_launch<N, 8>; else return nullptr;
+    case 16: if constexpr (fused_ok(N, 16)) return &fused_desc_launch<N, 16>; else return nullptr;
+    default: return nullptr;
+  }
+}
+
+static FusedDescFn fused_desc_fn(int N, int TP) {
+  switch (N) {
+    case 16: return fused_desc_for_taps<16>(TP);
+    case 32: return fused_desc_for_taps<32>(TP);
+    case 64: return fused_desc_for_taps<64>(TP);
+    case 128: return fused_desc_for_taps<128>(TP);
+    case 256: return fused_desc_for_taps<256>(TP);
+    case 512: return fused_desc_for_taps<512>(TP);
+    case 1024: return fused_desc_for_taps<1024>(TP);
+    case 2048: return fused_desc_for_taps<2048>(TP);
+    case 4096: return fused_desc_for_taps<4096>(TP);
+    case 8192: return fused_desc_for_taps<8192>(TP);
+    case 16384: return fused_desc_for_taps<16384>(TP);
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_fused_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                             hipStream_t st) {
+  FusedDescFn f = fused_desc_fn(pd.N, pd.TP);
+  if (!f) return hipErrorInvalidValue;
+  return f(pd, cls, tiles, max_tiles, pd.coef, pd.T, st);
+}
+
+hipError_t launch_fft_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                           hipStream_t st) {
+  FusedDescFn f = fused_desc_fn(pd.N, 1);
+  if (!f) return hipErrorInvalidValue;
+  return f(pd, cls, tiles, max_tiles, pd.ones, 1, st);
+}
+
+template <int TP>
+static hipError_t fir_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                                  hipStream_t st) {
+  constexpr int PF = TP >= 32 ? 2 : 4;
+  auto kern = &ppf_fir_desc_kernel<TP, PF>;
+  static const int occ = [&] {
+    KernelInfo ki{(const void*)kern, 256, 1, 0};
+    return occupancy(ki);
+  }();
+  if (!cls) return hipSuccess;                 // warm-up call: occupancy only
+  long long grid = (long long)device_cus() * occ;
+  const long long need = ((long long)max_tiles * pd.N + 255) / 256;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, st, cls, tiles, pd.coef, pd.N, TP - pd.T);
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
+                           hipStream_t st) {
+  switch (pd.TP) {
+    case 1: return fir_desc_launch<1>(pd, cls, tiles, max_tiles, st);
+    case 2: return fir_desc_launch<2>(pd, cls, tiles, max_tiles, st);
+    case 4: return fir_desc_launch<4>(pd, cls, tiles, max_tiles, st);
+    case 8: return fir_desc_launch<8>(pd, cls, tiles, max_tiles, st);
+    case 16: return fir_desc_launch<16>(pd, cls, tiles, max_tiles, st);
+    case 32: return fir_desc_launch<32>(pd, cls, tiles, max_tiles, st);
+    case 64: return fir_desc_launch<64>(pd, cls, tiles, max_tiles, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// First-use work of the descriptor launchers (occupancy queries, LDS
+// limits) done ahead of a graph capture.
+hipError_t prepare_desc(const PlanDev& pd, bool fused) {
+  hipError_t e = hipSuccess;
+  device_cus();
+  if (fused) {
+    e = launch_fused_desc(pd, nullptr, nullptr, 0, nullptr);
+  } else {
+    e = launch_fir_desc(pd, nullptr, nullptr, 0, nullptr);
+    if (e == hipSuccess) e = launch_fft_desc(pd, nullptr, nullptr, 0, nullptr);
+  }
+  return e;
+}
+
+hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, hipStream_t st) {
+  int grid = max_entries < 1 ? 1 : (max_entries > 1024 ? 1024 : max_entries);
+  hipLaunchKernelGGL(ppf_history_desc_kernel, dim3(grid), dim3(256), 0, st, count, h);
+  return hipGetLastError();
 }
 
 hipError_t launch_twiddles(void* tw, int N, hipStream_t st) {

@@ -10,9 +10,11 @@ library raises at load time, never falling back to anything else.
 from __future__ import annotations
 
 import ctypes
+import os
 import pathlib
 
-_LIB_PATH = pathlib.Path(__file__).resolve().with_name("libppf.so")
+# PPF_LIBRARY selects another build of the same library (tuning variants).
+_LIB_PATH = pathlib.Path(os.environ.get("PPF_LIBRARY") or pathlib.Path(__file__).resolve().with_name("libppf.so"))
 _lib = None
 
 # status codes (enum ppf_status)
@@ -40,6 +42,17 @@ _c_vp = ctypes.c_void_p
 _c_int = ctypes.c_int
 
 
+class ppf_chunk(ctypes.Structure):  # noqa: N801 - the C name
+    _fields_ = [("in_", _c_vp), ("out", _c_vp), ("nspectra", _c_ll), ("tag", ctypes.c_ulonglong)]
+
+
+class ppf_server_stats(ctypes.Structure):  # noqa: N801 - the C name
+    _fields_ = [(n, _c_ll) for n in ("chunks_done", "spectra_done", "bytes_in_done", "batches", "admitted",
+                                     "rejected", "queued_admissions", "state_bytes_used")] + \
+               [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "max_us", "mean_us", "elapsed_s",
+                                               "input_gbps", "mean_batch_chunks")]
+
+
 class PPFError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{status_str(status)} ({status}): {message}")
@@ -55,6 +68,23 @@ _SIGNATURES = [
     ("ppf_plan_query", _c_int, [_c_vp, _c_int, ctypes.POINTER(_c_ll)]),
     ("ppf_execute", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
     ("ppf_destroy", _c_int, [_c_vp]),
+    ("ppf_stream_create", _c_vp, [_c_vp]),
+    ("ppf_stream_push", _c_int, [_c_vp, _c_vp]),
+    ("ppf_stream_get_history", _c_int, [_c_vp, _c_vp]),
+    ("ppf_stream_set_history", _c_int, [_c_vp, _c_vp]),
+    ("ppf_stream_position", _c_ll, [_c_vp]),
+    ("ppf_stream_destroy", _c_int, [_c_vp]),
+    ("ppf_clock_ns", _c_ll, []),
+    ("ppf_server_create", _c_vp, [ctypes.c_size_t, _c_int]),
+    ("ppf_server_open_stream", _c_int, [_c_vp, _c_vp, _c_int, ctypes.POINTER(_c_int)]),
+    ("ppf_server_stream_admitted", _c_int, [_c_vp, _c_int]),
+    ("ppf_server_submit", _c_int, [_c_vp, _c_int, _c_vp, _c_ll]),
+    ("ppf_server_poll", _c_int, [_c_vp, ctypes.POINTER(ctypes.c_ulonglong), _c_int]),
+    ("ppf_server_drain", _c_int, [_c_vp, ctypes.c_double]),
+    ("ppf_server_close_stream", _c_int, [_c_vp, _c_int]),
+    ("ppf_server_get_stats", _c_int, [_c_vp, _c_vp]),
+    ("ppf_server_reset_stats", _c_int, [_c_vp]),
+    ("ppf_server_destroy", _c_int, [_c_vp]),
     ("ppf_last_error", _c_int, []),
     ("ppf_last_error_message", ctypes.c_char_p, []),
     ("ppf_status_str", ctypes.c_char_p, [_c_int]),
@@ -157,6 +187,94 @@ def ppf_execute(plan: int, inp, out, nspectra: int) -> int:
 
 def ppf_destroy(plan: int) -> int:
     return _check(lib().ppf_destroy(plan))
+
+
+def ppf_stream_create(plan: int) -> int:
+    return _handle(lib().ppf_stream_create(plan))
+
+
+def ppf_stream_push(stream: int, inp, out, nspectra: int, tag: int = 0) -> int:
+    ch = ppf_chunk(_addr(inp), _addr(out), int(nspectra), int(tag))
+    return _check(lib().ppf_stream_push(stream, ctypes.byref(ch)))
+
+
+def ppf_stream_get_history(stream: int, host_dst) -> int:
+    """host_dst: writable numpy array of (T-1)*N samples of the input type."""
+    return _check(lib().ppf_stream_get_history(stream, host_dst.ctypes.data))
+
+
+def ppf_stream_set_history(stream: int, host_src) -> int:
+    import numpy as np
+    src = np.ascontiguousarray(host_src)
+    return _check(lib().ppf_stream_set_history(stream, src.ctypes.data))
+
+
+def ppf_stream_position(stream: int) -> int:
+    v = int(lib().ppf_stream_position(stream))
+    if v < 0:
+        _check(last_error()[0])
+    return v
+
+
+def ppf_stream_destroy(stream: int) -> int:
+    return _check(lib().ppf_stream_destroy(stream))
+
+
+def ppf_clock_ns() -> int:
+    return int(lib().ppf_clock_ns())
+
+
+def ppf_server_create(hbm_budget_bytes: int, max_inflight: int = 2) -> int:
+    return _handle(lib().ppf_server_create(int(hbm_budget_bytes), int(max_inflight)))
+
+
+def ppf_server_open_stream(server: int, plan: int, wait_for_budget: bool = False) -> int:
+    sid = _c_int(-1)
+    _check(lib().ppf_server_open_stream(server, plan, int(bool(wait_for_budget)), ctypes.byref(sid)))
+    return int(sid.value)
+
+
+def ppf_server_stream_admitted(server: int, stream_id: int) -> bool:
+    r = int(lib().ppf_server_stream_admitted(server, int(stream_id)))
+    if r < 0:
+        _check(r)
+    return r == 1
+
+
+def ppf_server_submit(server: int, stream_id: int, inp, out, nspectra: int, tag: int = 0,
+                      arrival_ns: int = -1) -> int:
+    ch = ppf_chunk(_addr(inp), _addr(out), int(nspectra), int(tag))
+    return _check(lib().ppf_server_submit(server, int(stream_id), ctypes.byref(ch), int(arrival_ns)))
+
+
+def ppf_server_poll(server: int, max_tags: int = 4096) -> list[int]:
+    buf = (ctypes.c_ulonglong * max_tags)()
+    n = int(lib().ppf_server_poll(server, buf, int(max_tags)))
+    if n < 0:
+        _check(n)
+    return [int(buf[i]) for i in range(n)]
+
+
+def ppf_server_drain(server: int, timeout_s: float = 60.0) -> int:
+    return _check(lib().ppf_server_drain(server, float(timeout_s)))
+
+
+def ppf_server_close_stream(server: int, stream_id: int) -> int:
+    return _check(lib().ppf_server_close_stream(server, int(stream_id)))
+
+
+def ppf_server_get_stats(server: int) -> dict:
+    st = ppf_server_stats()
+    _check(lib().ppf_server_get_stats(server, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ppf_server_stats._fields_}
+
+
+def ppf_server_reset_stats(server: int) -> int:
+    return _check(lib().ppf_server_reset_stats(server))
+
+
+def ppf_server_destroy(server: int) -> int:
+    return _check(lib().ppf_server_destroy(server))
 
 
 # ---------------------------------------------------------------------------

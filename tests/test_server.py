@@ -1,0 +1,191 @@
+"""Serving form on the GPU: continuous batching of many streams of different
+N and T. Each stream's outputs must equal the oracle's stream PPF, and the
+same stream must give the same spectra alone and in the mix."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_3656_amd import ppf, signals
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+PLANS = [(256, 8), (1024, 8), (1024, 16), (4096, 16)]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_err(got, ref):
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    return float(np.max(np.abs(got - ref))) / rms
+
+
+class Workload:
+    """Streams with pre-generated chunk inputs (host and device) and outputs."""
+
+    def __init__(self, torch, n_streams, seed, max_spectra=40, chunks_per_stream=6):
+        rng = np.random.default_rng(seed)
+        self.torch = torch
+        self.coeffs = {}
+        self.streams = []
+        for i in range(n_streams):
+            n, taps = PLANS[int(rng.integers(len(PLANS)))] if i else PLANS[1]
+            lens = [int(v) for v in rng.integers(1, max_spectra + 1, chunks_per_stream)]
+            if n == 4096:
+                lens = [min(v, 12) for v in lens]
+            x = signals.complex_gaussian(sum(lens) * n, 1.0, seed=seed * 1000 + i)
+            chunks, at = [], 0
+            for s in lens:
+                chunks.append(x[at * n:(at + s) * n])
+                at += s
+            dev_in = [torch.from_numpy(c).cuda() for c in chunks]
+            self.streams.append(dict(n=n, taps=taps, lens=lens, chunks=chunks, dev_in=dev_in))
+        for n, taps in PLANS:
+            rng2 = np.random.default_rng(n * 7 + taps)
+            self.coeffs[(n, taps)] = rng2.standard_normal(taps * n).astype(np.float32)
+
+    def run(self, server, plans, which, order_seed):
+        """Submit the chunks of streams `which`, interleaved across streams in a
+        random order (in order within a stream); return outputs per stream."""
+        torch = self.torch
+        ids = {}
+        outs = {}
+        for k in which:
+            st = self.streams[k]
+            ids[k] = ppf.ppf_server_open_stream(server, plans[(st["n"], st["taps"])].handle)
+            outs[k] = [torch.full((s, st["n"]), float("nan"), dtype=torch.complex64, device="cuda")
+                       for s in st["lens"]]
+        cursor = {k: 0 for k in which}
+        rng = np.random.default_rng(order_seed)
+        live = list(which)
+        tags = []
+        while live:
+            k = live[int(rng.integers(len(live)))]
+            i = cursor[k]
+            st = self.streams[k]
+            tag = k * 1000 + i
+            ppf.ppf_server_submit(server, ids[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=tag)
+            tags.append(tag)
+            cursor[k] += 1
+            if cursor[k] == len(st["lens"]):
+                live.remove(k)
+        ppf.ppf_server_drain(server, 120.0)
+        done = []
+        while True:
+            got = ppf.ppf_server_poll(server)
+            if not got:
+                break
+            done.extend(got)
+        assert sorted(done) == sorted(tags)
+        for k in which:
+            ppf.ppf_server_close_stream(server, ids[k])
+        torch.cuda.synchronize()
+        return {k: np.concatenate([o.cpu().numpy() for o in outs[k]]) for k in which}
+
+
+def _plans(coeffs):
+    return {key: ppf.Plan(key[0], key[1], h) for key, h in coeffs.items()}
+
+
+def test_mix_matches_oracle_and_alone():
+    torch = _torch()
+    wl = Workload(torch, n_streams=12, seed=5)
+    plans = _plans(wl.coeffs)
+    srv = ppf.ppf_server_create(1 << 32, 2)
+    try:
+        mix = wl.run(srv, plans, list(range(12)), order_seed=1)
+        stats = ppf.ppf_server_get_stats(srv)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    assert stats["chunks_done"] == sum(len(s["lens"]) for s in wl.streams)
+    assert stats["batches"] >= 1 and stats["p99_us"] >= stats["p50_us"] > 0
+    for k, st in enumerate(wl.streams):
+        h = wl.coeffs[(st["n"], st["taps"])]
+        ref = np.concatenate(oracle.ppf_stream(st["chunks"], h, st["n"], st["taps"]))
+        assert mix[k].shape == ref.shape
+        err = rel_err(mix[k], ref)
+        print(f"stream {k} N={st['n']} T={st['taps']} chunks={st['lens']} err={err:.2e}")
+        assert err <= TOL, (k, err)
+    # stream 0 alone in a fresh server: same spectra
+    srv = ppf.ppf_server_create(1 << 32, 2)
+    try:
+        alone = wl.run(srv, plans, [0], order_seed=2)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    assert rel_err(alone[0], mix[0].astype(np.complex128)) <= TOL
+    assert np.array_equal(alone[0], mix[0])
+    for p in plans.values():
+        p.close()
+
+
+def test_budget_admission_queues_and_releases():
+    torch = _torch()
+    wl = Workload(torch, n_streams=1, seed=9, chunks_per_stream=1)
+    plans = _plans(wl.coeffs)
+    state = 2 * (8 - 1) * 1024 * 8 + 4096          # two history buffers + bookkeeping
+    probe = ppf.ppf_server_create(1 << 32, 2)
+    fixed = ppf.ppf_server_get_stats(probe)["state_bytes_used"]   # the server's own buffers
+    ppf.ppf_server_destroy(probe)
+    srv = ppf.ppf_server_create(fixed + 2 * state + 100, 2)
+    try:
+        key = (1024, 8)
+        a = ppf.ppf_server_open_stream(srv, plans[key].handle)
+        b = ppf.ppf_server_open_stream(srv, plans[key].handle)
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_server_open_stream(srv, plans[key].handle, wait_for_budget=False)
+        assert ei.value.status == ppf.PPF_ERR_BUDGET
+        c = ppf.ppf_server_open_stream(srv, plans[key].handle, wait_for_budget=True)
+        assert not ppf.ppf_server_stream_admitted(srv, c)
+        x = signals.complex_gaussian(20 * 1024, 1.0, seed=77)
+        xd = torch.from_numpy(x).cuda()
+        od = torch.empty((20, 1024), dtype=torch.complex64, device="cuda")
+        ppf.ppf_server_submit(srv, c, xd, od, 20, tag=7)     # waits with the stream
+        ppf.ppf_server_close_stream(srv, a)                   # frees budget: c is admitted
+        ppf.ppf_server_drain(srv, 60.0)
+        assert ppf.ppf_server_stream_admitted(srv, c)
+        assert ppf.ppf_server_poll(srv) == [7]
+        ref = oracle.ppf_stream([x], wl.coeffs[key], 1024, 8)[0]
+        assert rel_err(od.cpu().numpy(), ref) <= TOL
+        stats = ppf.ppf_server_get_stats(srv)
+        assert stats["rejected"] == 1 and stats["queued_admissions"] == 1
+        ppf.ppf_server_close_stream(srv, b)
+        ppf.ppf_server_close_stream(srv, c)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    for p in plans.values():
+        p.close()
+
+
+def test_submit_errors():
+    torch = _torch()
+    plan = ppf.Plan(256, 4, np.ones(1024, np.float32))
+    srv = ppf.ppf_server_create(1 << 30, 1)
+    try:
+        sid = ppf.ppf_server_open_stream(srv, plan.handle)
+        buf = torch.zeros(8 * 256, dtype=torch.complex64, device="cuda")
+        out = torch.empty_like(buf)
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_server_submit(srv, sid + 100, buf, out, 2)
+        assert ei.value.status == ppf.PPF_ERR_INVALID
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_server_submit(srv, sid, buf, out, 0)
+        assert ei.value.status == ppf.PPF_ERR_INVALID
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_server_submit(srv, sid, buf.data_ptr() + 8, out, 2)
+        assert ei.value.status == ppf.PPF_ERR_ALIGN
+        ppf.ppf_server_close_stream(srv, sid)
+        with pytest.raises(ppf.PPFError):
+            ppf.ppf_server_submit(srv, sid, buf, out, 2)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    with pytest.raises(ppf.PPFError) as ei:
+        ppf.ppf_server_create(1 << 20, 2)
+    assert ei.value.status == ppf.PPF_ERR_BUDGET
+    plan.close()
