@@ -122,6 +122,33 @@ def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_P
     return (ms, used_path, win_ms) if windows else (ms, used_path)
 
 
+def serve(load: float, seconds: float, warmup: float = 1.0) -> dict:
+    """Serving workload: 64 streams, N in {256, 1024, 4096}, T in {8, 16},
+    Poisson chunk arrivals of 1..64 spectra at `load` x 6.5 GB/s offered,
+    32 GB state budget; run by the native load generator."""
+    import subprocess
+    exe = ROOT / "paper_1411_3656_amd" / "ppf_serve_bench"
+    if not exe.exists():
+        return {"error": f"{exe} is not built"}
+    cmd = [str(exe), "--load", str(load), "--seconds", str(seconds), "--warmup", str(warmup), "--streams", "64",
+           "--seed", str(signals.SEED_BASE + 4), "--budget", "32e9", "--inflight", "2"]
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=seconds + warmup + 120)
+    if res.returncode != 0:
+        return {"error": "load generator failed", "stderr": res.stderr[-2000:], "stdout": res.stdout[-2000:]}
+    s = json.loads(res.stdout.strip().splitlines()[-1])
+    return {
+        "metric": METRIC, "value": s["sustained_gbps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": s["chunks"], "warmup": warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "realtime_multiple": s["realtime_multiple"],
+        "config": {"workload": s["workload"], "streams": 64, "N": [256, 1024, 4096], "taps": [8, 16],
+                   "chunk_spectra": [1, 64], "arrivals": "poisson", "offered_load_multiple": load,
+                   "offered_gbps": s["offered_gbps"], "state_budget_bytes": 32e9, "seconds": seconds},
+        "serving": {k: s[k] for k in ("p50_us", "p99_us", "max_us", "mean_us", "chunks", "batches",
+                                      "mean_batch_chunks", "chunk_rate_per_s", "late_submits", "mean_n")},
+    }
+
+
 def line(workload, n, taps, m_total, ms, used_path, steps, warmup, traffic=None, cpu=None):
     in_bytes = metrics.input_bytes(n, m_total)
     gbps = in_bytes / (ms * 1e-3) / 1e9
@@ -160,7 +187,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "sweep", "copy"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "sweep", "copy", "serve", "serve_sweep"])
+    ap.add_argument("--load", type=float, default=50.0, help="serving: offered load in multiples of 6.5 GB/s")
+    ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--windows", type=int, default=0,
@@ -178,6 +207,15 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         return 1
     path = {"auto": ppf.PPF_PATH_AUTO, "fused": ppf.PPF_PATH_FUSED, "two_pass": ppf.PPF_PATH_TWO_PASS}[args.path]
+
+    if args.workload in ("serve", "serve_sweep"):
+        loads = [args.load] if args.workload == "serve" else [50, 100, 150, 200, 300, 400]
+        for load in loads:
+            rec = serve(load, args.seconds)
+            print(json.dumps(rec), flush=True)
+            if rec.get("error"):
+                return 1
+        return 0
 
     if args.workload == "copy":
         # a plain device copy of known size: the yardstick for the HBM byte

@@ -228,6 +228,9 @@ typedef struct ppf_server_stats {
     double elapsed_s;             /* first arrival to last completion */
     double input_gbps;            /* bytes_in_done / elapsed_s / 1e9 */
     double mean_batch_chunks;
+    double mean_batch_gpu_us;     /* device time of a batch graph (timing events) */
+    double mean_form_us;          /* host time to form a batch */
+    double mean_launch_us;        /* host time of a graph launch */
 } ppf_server_stats;
 
 /* Host steady clock in nanoseconds (the time base of arrival times). */

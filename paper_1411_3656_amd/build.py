@@ -75,7 +75,25 @@ def build(jobs: int = 4, verbose: bool = False, defines=(), out: pathlib.Path | 
     os.replace(tmp, lib)
     if verbose:
         print(f"built {lib}", flush=True)
+    if out is None:
+        build_serve_bench(lib, verbose)
     return lib
+
+
+def build_serve_bench(lib: pathlib.Path, verbose: bool = False) -> pathlib.Path:
+    """The serving load generator, linked against the in-tree library."""
+    exe = PKG / "ppf_serve_bench"
+    tmp = exe.with_suffix(".tmp")
+    cmd = [hipcc(), *COMMON, "-x", "hip", str(CSRC / "serve_bench.cpp"), "-x", "none", f"-L{lib.parent}", "-lppf",
+           "-Wl,-rpath,$ORIGIN", "-o", str(tmp)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("build of ppf_serve_bench failed")
+    os.replace(tmp, exe)
+    if verbose:
+        print(f"built {exe}", flush=True)
+    return exe
 
 
 def main() -> None:

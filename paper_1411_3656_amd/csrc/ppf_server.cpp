@@ -95,6 +95,7 @@ struct Slot {
   DescArea* dev = nullptr;
   void* ws = nullptr;
   hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr;      // timing: recorded before the graph
   hipGraphExec_t exec = nullptr;
   int graph_classes = -1;          // class count the graph was captured for
   bool busy = false;
@@ -148,6 +149,8 @@ struct ppf_server_s {
   std::vector<double> lat_us;
   long long stat_chunks = 0, stat_spectra = 0, stat_bytes = 0, stat_batches = 0;
   long long stat_admitted = 0, stat_rejected = 0, stat_queued = 0;
+  double stat_gpu_us = 0, stat_form_us = 0, stat_launch_us = 0;
+  long long stat_timed = 0;
   long long first_arrival = -1, last_done = -1;
   long long outstanding = 0;       // submitted, not completed, all streams
   int next_id = 0;
@@ -356,6 +359,11 @@ int form_batch(ppf_server_s* s, Slot& sl) {
 
 // Record the chunks of a finished slot (mu held).
 void complete_slot(ppf_server_s* s, Slot& sl, long long t_done) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess) {
+    s->stat_gpu_us += ms * 1e3;
+    s->stat_timed++;
+  }
   for (const DoneChunk& dc : sl.chunks) {
     s->done_tags.push_back(dc.tag);
     s->lat_us.push_back((double)(t_done - dc.arrival_ns) * 1e-3);
@@ -447,12 +455,18 @@ void scheduler(ppf_server_s* s) {
           if (build_graph(s, s->slots[k]) != PPF_OK) s->async_error = PPF_ERR_HIP;
       }
       if (any_ready && sl.graph_classes == (int)s->classes.size() && s->async_error == PPF_OK) {
+        const long long tf0 = now_ns();
         const int n = form_batch(s, sl);
         if (n > 0) {
+          const long long tf1 = now_ns();
           lk.unlock();
-          hipError_t e = hipGraphLaunch(sl.exec, s->launch);
+          hipError_t e = hipEventRecord(sl.start, s->launch);
+          if (e == hipSuccess) e = hipGraphLaunch(sl.exec, s->launch);
           if (e == hipSuccess) e = hipEventRecord(sl.done, s->launch);
+          const long long tf2 = now_ns();
           lk.lock();
+          s->stat_form_us += (tf1 - tf0) * 1e-3;
+          s->stat_launch_us += (tf2 - tf1) * 1e-3;
           sl.busy = true;
           s->stat_batches++;
           s->next_slot = (s->next_slot + 1) % s->nslots;
@@ -481,6 +495,7 @@ void destroy_server(ppf_server_s* s) {
     Slot& sl = s->slots[k];
     if (sl.exec) hipGraphExecDestroy(sl.exec);
     if (sl.done) hipEventDestroy(sl.done);
+    if (sl.start) hipEventDestroy(sl.start);
     if (sl.host) hipHostFree(sl.host);
     if (sl.dev) hipFree(sl.dev);
     if (sl.ws) hipFree(sl.ws);
@@ -531,7 +546,8 @@ ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight) {
     if (e == hipSuccess) std::memset(sl.host, 0, sizeof(DescArea));
     if (e == hipSuccess) e = hipMalloc((void**)&sl.dev, sizeof(DescArea));
     if (e == hipSuccess) e = hipMalloc(&sl.ws, kSlotWorkspace);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&sl.done);
+    if (e == hipSuccess) e = hipEventCreate(&sl.start);
   }
   if (e != hipSuccess) {
     sfail_hip(e, "server creation");
@@ -680,6 +696,9 @@ int ppf_server_get_stats(ppf_server_t s, ppf_server_stats* out) {
     out->input_gbps = s->stat_bytes / out->elapsed_s / 1e9;
   }
   out->mean_batch_chunks = s->stat_batches ? (double)s->stat_chunks / s->stat_batches : 0.0;
+  out->mean_batch_gpu_us = s->stat_timed ? s->stat_gpu_us / s->stat_timed : 0.0;
+  out->mean_form_us = s->stat_batches ? s->stat_form_us / s->stat_batches : 0.0;
+  out->mean_launch_us = s->stat_batches ? s->stat_launch_us / s->stat_batches : 0.0;
   return PPF_OK;
 }
 
@@ -687,6 +706,8 @@ int ppf_server_reset_stats(ppf_server_t s) {
   if (!s) return sfail(PPF_ERR_INVALID, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   s->lat_us.clear();
+  s->stat_gpu_us = s->stat_form_us = s->stat_launch_us = 0;
+  s->stat_timed = 0;
   s->stat_chunks = s->stat_spectra = s->stat_bytes = s->stat_batches = 0;
   s->first_arrival = s->last_done = -1;
   return PPF_OK;

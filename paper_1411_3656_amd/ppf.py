@@ -50,7 +50,8 @@ class ppf_server_stats(ctypes.Structure):  # noqa: N801 - the C name
     _fields_ = [(n, _c_ll) for n in ("chunks_done", "spectra_done", "bytes_in_done", "batches", "admitted",
                                      "rejected", "queued_admissions", "state_bytes_used")] + \
                [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "max_us", "mean_us", "elapsed_s",
-                                               "input_gbps", "mean_batch_chunks")]
+                                               "input_gbps", "mean_batch_chunks", "mean_batch_gpu_us",
+                                               "mean_form_us", "mean_launch_us")]
 
 
 class PPFError(RuntimeError):
