@@ -95,10 +95,11 @@ def cpu_baseline(cfg, h32, budget_s: float = 12.0):
                       f"{total_s:.1f} s of FP64 numpy/BLAS"}
 
 
-def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO, windows=0):
+def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO, windows=0,
+              in_type=ppf.PPF_C32, coeff_shift=None):
     """Average ms per execute over `steps` after `warmup`; with windows > 0
     also the average of each of `windows` consecutive slices of the steps."""
-    plan = ppf.Plan(n, taps, h32, path)
+    plan = ppf.Plan(n, taps, h32, path, in_type=in_type, coeff_shift=coeff_shift)
     out = torch.empty((m_total, n), dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
     ppf.ppf_set_stream(plan.handle, stream.cuda_stream)
@@ -187,7 +188,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "sweep", "copy", "serve", "serve_sweep"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep"])
     ap.add_argument("--load", type=float, default=50.0, help="serving: offered load in multiples of 6.5 GB/s")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
@@ -215,6 +216,38 @@ def main() -> int:
             print(json.dumps(rec), flush=True)
             if rec.get("error"):
                 return 1
+        return 0
+
+    if args.workload == "c4":
+        # precision form: complex int8 input (sigma 16), FP16 coefficients with
+        # a 2^s scale, FP32 accumulation; beside it the FP32 path on the same values
+        n, taps, n_samples = 4096, 16, 1 << 28
+        m_total = n_samples // n - taps + 1
+        x = signals.int8_input(n_samples, seed=signals.SEED_BASE + 3, sigma=16.0)
+        x_dev = torch.from_numpy(x).cuda()
+        del x
+        h64 = signals.design_coeffs(n, taps, "hamming")
+        h16, shift = signals.coeffs_fp16(h64)
+        ms8, used8 = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup,
+                               in_type=ppf.PPF_CI8, coeff_shift=shift)
+        rec = line("precision_n4096_t16_int8_fp16coef_2p28", n, taps, m_total, ms8, used8, args.steps,
+                   args.warmup, measured_traffic("c4"))
+        in_b = metrics.input_bytes(n, m_total, 2)
+        rec["value"] = round(in_b / (ms8 * 1e-3) / 1e9, 3)
+        rec["realtime_multiple"] = round(metrics.realtime_multiple(rec["value"] * 1e9), 2)
+        rec["dtype"] = "ci8_in/f16_coef/f32_acc"
+        alg = metrics.algorithmic_bytes(n, taps, m_total, in_bytes=2, out_bytes=8, coeff_bytes=2)
+        rec["roofline"].update({"achieved": round(alg / (ms8 * 1e-3) / 1e9, 2), "algorithmic_bytes": alg})
+        rec["roofline"]["frac"] = round(rec["roofline"]["achieved"] / rec["roofline"]["peak"], 4)
+        x32 = torch.view_as_complex(x_dev.to(torch.float32).contiguous())
+        del x_dev
+        ms32, used32 = run_point(torch, n, taps, m_total, x32, h64.astype(np.float32), args.steps, args.warmup)
+        rec["fp32_path_same_values"] = {"ms_per_step": round(ms32, 5),
+                                        "input_gbps_fp32": round(metrics.input_bytes(n, m_total) / (ms32 * 1e-3) / 1e9, 3),
+                                        "samples_per_s": round(n * m_total / (ms32 * 1e-3), 1),
+                                        "path": {1: "fused", 2: "two_pass"}.get(used32)}
+        rec["samples_per_s"] = round(n * m_total / (ms8 * 1e-3), 1)
+        print(json.dumps(rec), flush=True)
         return 0
 
     if args.workload == "copy":

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -48,6 +49,36 @@ int sample_bytes(int dtype) {
 
 bool overlaps(uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; }
 
+// IEEE binary16 -> binary32 (exact)
+float half_to_float(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+  uint32_t exp = (h >> 10) & 0x1Fu;
+  uint32_t man = h & 0x3FFu;
+  uint32_t bits;
+  if (exp == 0) {
+    if (man == 0) {
+      bits = sign;
+    } else {                       // subnormal: normalise
+      int e = -1;
+      do { man <<= 1; ++e; } while (!(man & 0x400u));
+      bits = sign | ((uint32_t)(127 - 15 - e) << 23) | ((man & 0x3FFu) << 13);
+    }
+  } else if (exp == 31) {
+    bits = sign | 0x7F800000u | (man << 13);
+  } else {
+    bits = sign | ((exp - 15 + 127) << 23) | (man << 13);
+  }
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return f;
+}
+
+// The fused kernels read complex FP32 input; other input types take the
+// two-pass path, whose FIR pass widens them as it loads.
+bool fused_ok_for(int N, int TP, int in_type) {
+  return in_type == PPF_C32 && (ppf::fused_available(N, TP) || TP == 1);
+}
+
 // Largest FIR workspace of the two-pass path, in bytes (stays inside the
 // 256 MB Infinity Cache between the FIR and the FFT launch of a chunk).
 constexpr size_t kWorkspaceBytes = 64ull << 20;
@@ -74,6 +105,7 @@ struct ppf_plan_s {
     p.coef = d_coef;
     p.ones = d_ones;
     p.tw = d_tw;
+    p.in_type = in_type == PPF_C32 ? 0 : (in_type == PPF_C16 ? 1 : 2);
     return p;
   }
   ~ppf_plan_s() {
@@ -172,8 +204,8 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
     return nullptr;
   }
   if (coeff_shift < 0 || coeff_shift > 30) { fail(PPF_ERR_INVALID, "coeff_shift=%d outside 0..30", coeff_shift); return nullptr; }
-  if (coeff_type != PPF_R32 || in_type != PPF_C32 || fft_mode != PPF_FFT_F32) {
-    fail(PPF_ERR_UNSUPPORTED, "only float32 coefficients, complex float32 input and the FP32 FFT are built");
+  if (fft_mode != PPF_FFT_F32) {
+    fail(PPF_ERR_UNSUPPORTED, "fft_mode=%d is not built for N=%d taps=%d", fft_mode, N, taps);
     return nullptr;
   }
   if (!ppf::fft_available(N) || !ppf::fir_available(TP)) {
@@ -190,11 +222,18 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   p->coeff_type = coeff_type;
   p->coeff_shift = coeff_shift;
   p->fft_mode = fft_mode;
-  p->path = ppf::fused_available(N, TP) || TP == 1 ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+  p->path = fused_ok_for(N, TP, in_type) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
 
-  // coefficients padded at the front with TP-T zero segments
+  // coefficients padded at the front with TP-T zero segments; FP16
+  // coefficients are widened exactly and the 2^-shift is applied (exact)
   std::vector<float> hpad((size_t)TP * N, 0.0f);
-  std::memcpy(hpad.data() + (size_t)(TP - taps) * N, coeffs, (size_t)taps * N * sizeof(float));
+  if (coeff_type == PPF_R32) {
+    std::memcpy(hpad.data() + (size_t)(TP - taps) * N, coeffs, (size_t)taps * N * sizeof(float));
+  } else {
+    const uint16_t* h16 = (const uint16_t*)coeffs;
+    const float scale = std::ldexp(1.0f, -coeff_shift);
+    for (size_t i = 0; i < (size_t)taps * N; ++i) hpad[(size_t)(TP - taps) * N + i] = half_to_float(h16[i]) * scale;
+  }
   std::vector<float> ones((size_t)N, 1.0f);
 
   hipError_t e;
@@ -254,10 +293,10 @@ int ppf_plan_set_path(ppf_plan_t plan, int path) {
   if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
   switch (path) {
     case PPF_PATH_AUTO:
-      plan->path = ppf::fused_available(plan->N, plan->TP) || plan->TP == 1 ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+      plan->path = fused_ok_for(plan->N, plan->TP, plan->in_type) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
       return PPF_OK;
     case PPF_PATH_FUSED:
-      if (!(ppf::fused_available(plan->N, plan->TP) || plan->TP == 1))
+      if (!fused_ok_for(plan->N, plan->TP, plan->in_type))
         return fail(PPF_ERR_UNSUPPORTED, "no fused kernel for N=%d taps=%d", plan->N, plan->T);
       plan->path = PPF_PATH_FUSED;
       return PPF_OK;
@@ -280,7 +319,7 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value) {
     case PPF_Q_IN_TYPE: *value = plan->in_type; return PPF_OK;
     case PPF_Q_FFT_MODE: *value = plan->fft_mode; return PPF_OK;
     case PPF_Q_COEFF_SHIFT: *value = plan->coeff_shift; return PPF_OK;
-    case PPF_Q_FUSED_AVAILABLE: *value = (ppf::fused_available(plan->N, plan->TP) || plan->TP == 1) ? 1 : 0; return PPF_OK;
+    case PPF_Q_FUSED_AVAILABLE: *value = fused_ok_for(plan->N, plan->TP, plan->in_type) ? 1 : 0; return PPF_OK;
     default: return fail(PPF_ERR_INVALID, "query key %d unknown", key);
   }
 }

@@ -28,6 +28,7 @@ struct PlanDev {
   const float* coef;   // TP*N, zero-padded at the front (TP-T leading zero segments)
   const float* ones;   // N ones: identity coefficients for the FFT-only pass
   const void* tw;      // N complex FP32 twiddles exp(-2 pi i k/N)
+  int in_type;         // 0 complex FP32, 1 complex FP16, 2 complex int8
 };
 
 // Descriptor tables of the serving form (device memory, filled by the host).

@@ -190,7 +190,11 @@ constexpr int tw_total(int N, int R, int RX) { return tw_offset(N, R, RX, num_st
 // planes by W words.
 template <int N>
 __device__ __forceinline__ int lds_index(int i) {
-  if constexpr (N >= 256) {
+  if constexpr (N >= 8192) {
+    // plain layout: every stage's addresses are one per-thread base plus
+    // immediates, which keeps 16 elements per thread within the registers
+    return i;
+  } else if constexpr (N >= 256) {
     const int row = i >> 6;
     return i ^ ((row ^ (row << 2) ^ (row << 4)) & 63);
   } else {
@@ -198,6 +202,7 @@ __device__ __forceinline__ int lds_index(int i) {
   }
 }
 constexpr int plane_floats(int N, int W) {
+  if (N >= 8192) return N;
   if (N >= 256) return N;
   const int p = N + N / 32;
   return W < 32 ? ((p + 31) / 32) * 32 + W : p;
@@ -256,8 +261,13 @@ struct GroupFft {
   __device__ __forceinline__ v2f twiddle(int i, int q) const {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     if constexpr (TWG) {
+      // read at the point of use: the address is loop-invariant, and a
+      // hoisted load would keep every stage's twiddles live in registers;
+      // an opaque zero ties the load to this stage
+      int z;
+      asm volatile("s_mov_b32 %0, 0" : "=s"(z));
       const int k = (j + i * W) % Ns;
-      return tw[k * q * (N / (Ns * r))];
+      return tw[k * q * (N / (Ns * r)) + z];
     } else {
       const int ib = (Ns <= W) ? 0 : i;
       return twr[tw_offset(N, R, RX, S) + ib * (r - 1) + q - 1];
@@ -365,6 +375,24 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 #endif
 constexpr bool kNtLoads = PPF_NT_LOADS != 0;
 
+// Raw buffer access (gfx9 descriptor): a scalar resource per block of N
+// samples, a 32-bit per-thread offset, and each element's extra offset as
+// a scalar constant. Reads outside the block's range return zero.
+constexpr int kBufDword3 = 0x00020000;
+constexpr int kAuxNt = 2;   // non-temporal cache policy bit of buffer instructions
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kBufDword3);
+}
+template <int AUX>
+__device__ __forceinline__ v2f buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void buf_store(v2f v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                        r, voff, soff, AUX);
+}
+
 // Block and spectrum indices of one launch fit in 32 bits (the host splits
 // larger batches), so their arithmetic and compares stay on the scalar unit.
 struct FusedParams {
@@ -403,29 +431,33 @@ __device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
 // step; the B blocks loaded at a step replace the B oldest, which no later
 // spectrum needs, so any Q >= TP + B - 1 is hazard-free and PF - B + 1
 // blocks of each step are loads running ahead.
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
+// UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
+// presum is the loaded block itself and no coefficients are held.
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
 struct FusedEngine {
   static constexpr int W = N / R;
   static constexpr int Q = TP + PF;
   static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
+  static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
 
   Fft fft;
   int j;
   int d;
-  float hreg[TP][R];
-  uint32_t loff[R];    // byte offset of this thread's channels inside a block
+  float hreg[UNIT ? 1 : TP][R];
+  uint32_t loff;       // byte offset of channel j inside a block; element e adds e*W*8
 
   __device__ __forceinline__ void init(float* smem, int grp, int j_, const float* coef, const v2f* tw, int d_) {
     j = j_;
     d = d_;
     fft.init(smem, grp, j, tw);
+    if constexpr (!UNIT) {
 #pragma unroll
-    for (int t = 0; t < TP; ++t)
+      for (int t = 0; t < TP; ++t)
 #pragma unroll
-      for (int e = 0; e < R; ++e) hreg[t][e] = coef[t * N + j + e * W];
-#pragma unroll
-    for (int e = 0; e < R; ++e) loff[e] = (uint32_t)(j + e * W) * (uint32_t)sizeof(v2f);
+        for (int e = 0; e < R; ++e) hreg[t][e] = coef[t * N + j + e * W];
+    }
+    loff = (uint32_t)j * (uint32_t)sizeof(v2f);
   }
 
   // Spectra m0 .. m0+ng-1 of the tile; niter >= ng is the same for every
@@ -447,12 +479,10 @@ struct FusedEngine {
     auto load = [&](v2f (&dst)[R], int vb) {
       if (vb >= vb_lo && vb < vb_hi) {
         if constexpr (G == 1) {
-          const char* bp = (const char*)block_ptr<N>(a, vb - d);
+          const __amdgpu_buffer_rsrc_t rs = block_rsrc(block_ptr<N>(a, vb - d), N * (int)sizeof(v2f));
 #pragma unroll
-          for (int e = 0; e < R; ++e) {
-            if constexpr (kNtLoads) dst[e] = __builtin_nontemporal_load((const v2f*)(bp + loff[e]));
-            else dst[e] = *(const v2f*)(bp + loff[e]);
-          }
+          for (int e = 0; e < R; ++e)
+            dst[e] = buf_load<kNtLoads ? kAuxNt : 0>(rs, loff, (uint32_t)(e * W * (int)sizeof(v2f)));
         } else {
           const v2f* src = block_ptr<N>(a, vb - d) + j;
 #pragma unroll
@@ -476,24 +506,29 @@ struct FusedEngine {
         for (int b = 0; b < B; ++b)
 #pragma unroll
           for (int e = 0; e < R; ++e) {
-            v2f acc;
-            acc.x = hreg[0][e] * ring[(k + b) % Q][e].x;
-            acc.y = hreg[0][e] * ring[(k + b) % Q][e].y;
+            if constexpr (UNIT) {
+              v[b][e] = ring[(k + b) % Q][e];
+            } else {
+              v2f acc;
+              acc.x = hreg[0][e] * ring[(k + b) % Q][e].x;
+              acc.y = hreg[0][e] * ring[(k + b) % Q][e].y;
 #pragma unroll
-            for (int t = 1; t < TP; ++t) {
-              acc.x = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].x, acc.x);
-              acc.y = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].y, acc.y);
+              for (int t = 1; t < TP; ++t) {
+                acc.x = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].x, acc.x);
+                acc.y = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].y, acc.y);
+              }
+              v[b][e] = acc;
             }
-            v[b][e] = acc;
           }
         fft.run(v);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           if (it + b < ng) {
             if constexpr (G == 1) {
-              char* ob = (char*)(a.out + (long long)(m0 + it + b) * N);
+              const __amdgpu_buffer_rsrc_t rs =
+                  block_rsrc(a.out + (long long)(m0 + it + b) * N, N * (int)sizeof(v2f));
 #pragma unroll
-              for (int e = 0; e < R; ++e) __builtin_nontemporal_store(v[b][e], (v2f*)(ob + loff[e]));
+              for (int e = 0; e < R; ++e) buf_store<kAuxNt>(v[b][e], rs, loff, (uint32_t)(e * W * (int)sizeof(v2f)));
             } else {
               v2f* dst = a.out + (long long)(m0 + it + b) * N + j;
 #pragma unroll
@@ -508,7 +543,7 @@ struct FusedEngine {
 
 // Batch form: a wave of tiles of S consecutive spectra covers the batch;
 // group g of block lb owns the tile (lb*G + g).
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
 __global__ void __launch_bounds__((N / R) * G)
 ppf_fused_kernel(FusedParams p) {
   constexpr int W = N / R;
@@ -525,7 +560,7 @@ ppf_fused_kernel(FusedParams p) {
   const int brem = p.M - blk_m0;
   const int niter = brem < p.S ? brem : p.S;                   // uniform over the block
 
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG> eng;
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT> eng;
   eng.init(smem, grp, j, p.coef, p.tw, p.d);
   TileArgs a{p.x0, p.x1, p.out, p.h0};
   eng.run(a, m0, ng, niter);
@@ -535,7 +570,7 @@ ppf_fused_kernel(FusedParams p) {
 // persistent grid walks them, G tiles per block at a time. Every wave of a
 // block exits at the same tile index, after the same number of barriers.
 
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG>
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
 __global__ void __launch_bounds__((N / R) * G)
 ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, const v2f* tw, int d) {
   constexpr int W = N / R;
@@ -547,7 +582,7 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
   const int first = cls->first;
   const int ntiles = cls->ntiles;
   if ((int)blockIdx.x * G >= ntiles) return;                  // whole block idle
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG> eng;
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT> eng;
   eng.init(smem, grp, j, coef, tw, d);
   for (int t0 = blockIdx.x * G; t0 < ntiles; t0 += gridDim.x * G) {
     const int t = t0 + grp;
@@ -576,8 +611,8 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
 // --------------------------------------------------------------------------
 
 struct FirParams {
-  const v2f* x0;
-  const v2f* x1;
+  const void* x0;
+  const void* x1;
   v2f* out;            // u, M*N
   const float* coef;   // TP*N
   int h0;
@@ -587,7 +622,32 @@ struct FirParams {
   int d;
 };
 
-template <int TP, int PF>
+// Stored complex input types, widened to FP32 as they are loaded:
+// 0 = complex FP32, 1 = complex FP16, 2 = complex int8 (exact conversions).
+template <int IT>
+__device__ __forceinline__ v2f load_sample(const void* base, long long i) {
+  if constexpr (IT == 0) {
+    return ((const v2f*)base)[i];
+  } else if constexpr (IT == 1) {
+    const uint32_t w = ((const uint32_t*)base)[i];
+    _Float16 re, im;
+    const uint16_t lo = (uint16_t)(w & 0xFFFFu), hi = (uint16_t)(w >> 16);
+    __builtin_memcpy(&re, &lo, 2);
+    __builtin_memcpy(&im, &hi, 2);
+    v2f r;
+    r.x = (float)re;
+    r.y = (float)im;
+    return r;
+  } else {
+    const uint16_t w = ((const uint16_t*)base)[i];
+    v2f r;
+    r.x = (float)(int)(int8_t)(w & 0xFFu);
+    r.y = (float)(int)(int8_t)(w >> 8);
+    return r;
+  }
+}
+
+template <int TP, int PF, int IT>
 __global__ void __launch_bounds__(256) ppf_fir_kernel(FirParams p) {
   constexpr int Q = TP + PF;
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -610,7 +670,8 @@ __global__ void __launch_bounds__(256) ppf_fir_kernel(FirParams p) {
   auto load = [&](v2f& dst, int vb) {
     if (vb >= vb_lo && vb < vb_hi) {
       const int rb = vb - p.d;
-      dst = rb < p.h0 ? p.x0[(long long)rb * p.N + c] : p.x1[(long long)(rb - p.h0) * p.N + c];
+      dst = rb < p.h0 ? load_sample<IT>(p.x0, (long long)rb * p.N + c)
+                      : load_sample<IT>(p.x1, (long long)(rb - p.h0) * p.N + c);
     }
   };
 #pragma unroll
@@ -734,7 +795,7 @@ __global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count,
 #endif
 
 // elements per thread R and groups per block G for the FFT of N points
-constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : (N <= 8192 ? 16 : 32)); }
+constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : 16); }
 constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
 constexpr int cfg_W(int N) { return N / cfg_R(N); }
 constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
@@ -782,12 +843,12 @@ static int occupancy(const KernelInfo& ki) {
   return occ;
 }
 
-template <int N, int TP>
+template <int N, int TP, bool UNIT>
 static const KernelInfo& fused_info() {
   constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
-  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG>,
+  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>,
                              (N / R) * G, G, Fft::lds_bytes()};
   return ki;
 }
@@ -813,10 +874,10 @@ static BatchArgs sub_batch(const BatchArgs& a, int N, size_t sample_bytes, long 
   return o;
 }
 
-template <int N, int TP>
+template <int N, int TP, bool UNIT>
 static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const float* coef, int T,
                                    hipStream_t st) {
-  const KernelInfo& ki = fused_info<N, TP>();
+  const KernelInfo& ki = fused_info<N, TP, UNIT>();
   static const int occ = occupancy(ki);
   const long long resident_groups = (long long)device_cus() * occ * ki.G;
   long long S = (a.M + resident_groups - 1) / resident_groups;
@@ -837,16 +898,16 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   p.nblocks = (int)nblocks;
   constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG>), dim3((unsigned)nblocks), dim3(ki.block),
+  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>), dim3((unsigned)nblocks), dim3(ki.block),
                      ki.lds, st, p);
   return hipGetLastError();
 }
 
-template <int N, int TP>
+template <int N, int TP, bool UNIT = false>
 static hipError_t fused_launch(const PlanDev& pd, const BatchArgs& a, const float* coef, int T, hipStream_t st) {
   for (long long s0 = 0; s0 < a.M; s0 += kMaxLaunchSpectra) {
     const long long k = a.M - s0 < kMaxLaunchSpectra ? a.M - s0 : kMaxLaunchSpectra;
-    const hipError_t e = fused_launch_one<N, TP>(pd, sub_batch(a, N, 8, s0, k), coef, T, st);
+    const hipError_t e = fused_launch_one<N, TP, UNIT>(pd, sub_batch(a, N, 8, s0, k), coef, T, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -905,18 +966,35 @@ hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
   return f(pd, a, pd.coef, pd.T, st);
 }
 
+static FusedFn fft_fn(int N) {
+  switch (N) {
+    case 16: return &fused_launch<16, 1, true>;
+    case 32: return &fused_launch<32, 1, true>;
+    case 64: return &fused_launch<64, 1, true>;
+    case 128: return &fused_launch<128, 1, true>;
+    case 256: return &fused_launch<256, 1, true>;
+    case 512: return &fused_launch<512, 1, true>;
+    case 1024: return &fused_launch<1024, 1, true>;
+    case 2048: return &fused_launch<2048, 1, true>;
+    case 4096: return &fused_launch<4096, 1, true>;
+    case 8192: return &fused_launch<8192, 1, true>;
+    case 16384: return &fused_launch<16384, 1, true>;
+    default: return nullptr;
+  }
+}
+
 hipError_t launch_fft(const PlanDev& pd, const void* in, void* out, long long M, hipStream_t st) {
-  FusedFn f = fused_fn(pd.N, 1);
+  FusedFn f = fft_fn(pd.N);
   if (!f) return hipErrorInvalidValue;
   BatchArgs a{in, in, 0, out, M};
   return f(pd, a, pd.ones, 1, st);
 }
 
-template <int TP>
+template <int TP, int IT>
 static hipError_t fir_launch(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
   constexpr int PF = TP >= 32 ? 2 : 4;
   static const int occ = [] {
-    KernelInfo ki{(const void*)&ppf_fir_kernel<TP, PF>, 256, 1, 0};
+    KernelInfo ki{(const void*)&ppf_fir_kernel<TP, PF, IT>, 256, 1, 0};
     return occupancy(ki);
   }();
   const long long resident = (long long)device_cus() * occ * 256;   // threads
@@ -934,8 +1012,8 @@ static hipError_t fir_launch(const PlanDev& pd, const BatchArgs& a, hipStream_t 
   if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
   if (a.M > kMaxLaunchSpectra || a.h0 > kMaxLaunchSpectra) return hipErrorInvalidValue;
   FirParams p;
-  p.x0 = (const v2f*)a.x0;
-  p.x1 = (const v2f*)a.x1;
+  p.x0 = a.x0;
+  p.x1 = a.x1;
   p.out = (v2f*)a.out;
   p.coef = pd.coef;
   p.h0 = (int)a.h0;
@@ -943,7 +1021,7 @@ static hipError_t fir_launch(const PlanDev& pd, const BatchArgs& a, hipStream_t 
   p.N = pd.N;
   p.S = (int)S;
   p.d = TP - pd.T;
-  hipLaunchKernelGGL((ppf_fir_kernel<TP, PF>), dim3((unsigned)nblocks), dim3(256), 0, st, p);
+  hipLaunchKernelGGL((ppf_fir_kernel<TP, PF, IT>), dim3((unsigned)nblocks), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
@@ -951,28 +1029,38 @@ bool fir_available(int TP) {
   return TP == 1 || TP == 2 || TP == 4 || TP == 8 || TP == 16 || TP == 32 || TP == 64;
 }
 
-hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
+template <int IT>
+static hipError_t fir_launch_taps(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
   switch (pd.TP) {
-    case 1: return fir_launch<1>(pd, a, st);
-    case 2: return fir_launch<2>(pd, a, st);
-    case 4: return fir_launch<4>(pd, a, st);
-    case 8: return fir_launch<8>(pd, a, st);
-    case 16: return fir_launch<16>(pd, a, st);
-    case 32: return fir_launch<32>(pd, a, st);
-    case 64: return fir_launch<64>(pd, a, st);
+    case 1: return fir_launch<1, IT>(pd, a, st);
+    case 2: return fir_launch<2, IT>(pd, a, st);
+    case 4: return fir_launch<4, IT>(pd, a, st);
+    case 8: return fir_launch<8, IT>(pd, a, st);
+    case 16: return fir_launch<16, IT>(pd, a, st);
+    case 32: return fir_launch<32, IT>(pd, a, st);
+    case 64: return fir_launch<64, IT>(pd, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
+  switch (pd.in_type) {
+    case 0: return fir_launch_taps<0>(pd, a, st);
+    case 1: return fir_launch_taps<1>(pd, a, st);
+    case 2: return fir_launch_taps<2>(pd, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---- descriptor launchers (persistent grids, fixed across graph replays)
 
-template <int N, int TP>
+template <int N, int TP, bool UNIT = false>
 static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                                     const float* coef, int T, hipStream_t st) {
   constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
-  auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG>;
+  auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   static const int occ = [&] {
     KernelInfo ki{(const void*)kern, (N / R) * G, G, Fft::lds_bytes()};
     return occupancy(ki);
@@ -1026,9 +1114,26 @@ hipError_t launch_fused_desc(const PlanDev& pd, const DescClass* cls, const Tile
   return f(pd, cls, tiles, max_tiles, pd.coef, pd.T, st);
 }
 
+static FusedDescFn fft_desc_fn(int N) {
+  switch (N) {
+    case 16: return &fused_desc_launch<16, 1, true>;
+    case 32: return &fused_desc_launch<32, 1, true>;
+    case 64: return &fused_desc_launch<64, 1, true>;
+    case 128: return &fused_desc_launch<128, 1, true>;
+    case 256: return &fused_desc_launch<256, 1, true>;
+    case 512: return &fused_desc_launch<512, 1, true>;
+    case 1024: return &fused_desc_launch<1024, 1, true>;
+    case 2048: return &fused_desc_launch<2048, 1, true>;
+    case 4096: return &fused_desc_launch<4096, 1, true>;
+    case 8192: return &fused_desc_launch<8192, 1, true>;
+    case 16384: return &fused_desc_launch<16384, 1, true>;
+    default: return nullptr;
+  }
+}
+
 hipError_t launch_fft_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                            hipStream_t st) {
-  FusedDescFn f = fused_desc_fn(pd.N, 1);
+  FusedDescFn f = fft_desc_fn(pd.N);
   if (!f) return hipErrorInvalidValue;
   return f(pd, cls, tiles, max_tiles, pd.ones, 1, st);
 }

@@ -283,11 +283,25 @@ def ppf_server_destroy(server: int) -> int:
 # ---------------------------------------------------------------------------
 
 class Plan:
-    """Owning wrapper of a ppf_plan_t bound to torch's current stream."""
+    """Owning wrapper of a ppf_plan_t bound to torch's current stream.
 
-    def __init__(self, n_channels: int, taps: int, coeffs, path: int = PPF_PATH_AUTO):
+    coeffs: float32 (any precision input) or float16 with ``coeff_shift``
+    (stored values are h * 2^coeff_shift). in_type: PPF_C32, PPF_C16 or
+    PPF_CI8; complex FP16/int8 inputs are (L, 2) tensors of (re, im).
+    """
+
+    def __init__(self, n_channels: int, taps: int, coeffs, path: int = PPF_PATH_AUTO,
+                 in_type: int = PPF_C32, coeff_shift: int | None = None, fft_mode: int = PPF_FFT_F32):
+        import numpy as np
         self.N, self.T = int(n_channels), int(taps)
-        self.handle = ppf_plan(self.N, self.T, coeffs)
+        self.in_type = int(in_type)
+        h = np.asarray(coeffs)
+        if h.dtype == np.float16:
+            self.handle = ppf_plan_ex(self.N, self.T, h, PPF_R16, int(coeff_shift or 0), self.in_type, fft_mode)
+        elif self.in_type == PPF_C32 and fft_mode == PPF_FFT_F32:
+            self.handle = ppf_plan(self.N, self.T, h)
+        else:
+            self.handle = ppf_plan_ex(self.N, self.T, h.astype(np.float32), PPF_R32, 0, self.in_type, fft_mode)
         if path != PPF_PATH_AUTO:
             ppf_plan_set_path(self.handle, path)
 
@@ -299,7 +313,8 @@ class Plan:
         """x: complex64 CUDA tensor of (M+T-1)*N samples; returns (M, N) complex64."""
         import torch
         if nspectra is None:
-            nspectra = x.numel() // self.N - self.T + 1
+            samples = x.numel() if x.is_complex() else x.shape[0]
+            nspectra = samples // self.N - self.T + 1
         if out is None:
             out = torch.empty((nspectra, self.N), dtype=torch.complex64, device=x.device)
         st = torch.cuda.current_stream(x.device) if stream is None else stream
