@@ -34,7 +34,10 @@ from paper_1411_3656_amd import metrics, ppf, signals  # noqa: E402
 
 METRIC = "PPF input GB/s (×6.5 GB/s real-time), % HBM peak; p99 stream chunk latency"
 PROFILES = ROOT / "profiles"
-KERNEL_SOURCES = [ROOT / "paper_1411_3656_amd" / "csrc" / "ppf_kernels.hip"]
+CSRC = ROOT / "paper_1411_3656_amd" / "csrc"
+# the kernel source each workload's dominant kernel is built from
+KERNEL_SOURCES = {"c4": [CSRC / "ppf_mfma.hip"]}
+DEFAULT_KERNEL_SOURCES = [CSRC / "ppf_kernels.hip"]
 
 WORKLOADS = {
     "c1": dict(name="plain_n256_t8_16384spectra", N=256, T=8, window="hamming", spectra=16384, tones=True,
@@ -46,9 +49,9 @@ SWEEP_N = [64, 512, 4096, 16384]
 SWEEP_T = [4, 8, 16, 32]
 
 
-def kernel_hash() -> str:
+def kernel_hash(workload: str = "c2") -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES.get(workload, DEFAULT_KERNEL_SOURCES):
         h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
@@ -66,7 +69,7 @@ def measured_traffic(workload: str):
         rec = json.loads(f.read_text())
     except ValueError:
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(workload):
         return None
     return rec.get("bytes_per_launch")
 
@@ -96,10 +99,10 @@ def cpu_baseline(cfg, h32, budget_s: float = 12.0):
 
 
 def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO, windows=0,
-              in_type=ppf.PPF_C32, coeff_shift=None):
+              in_type=ppf.PPF_C32, coeff_shift=None, fft_mode=ppf.PPF_FFT_F32):
     """Average ms per execute over `steps` after `warmup`; with windows > 0
     also the average of each of `windows` consecutive slices of the steps."""
-    plan = ppf.Plan(n, taps, h32, path, in_type=in_type, coeff_shift=coeff_shift)
+    plan = ppf.Plan(n, taps, h32, path, in_type=in_type, coeff_shift=coeff_shift, fft_mode=fft_mode)
     out = torch.empty((m_total, n), dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
     ppf.ppf_set_stream(plan.handle, stream.cuda_stream)
@@ -220,7 +223,9 @@ def main() -> int:
 
     if args.workload == "c4":
         # precision form: complex int8 input (sigma 16), FP16 coefficients with
-        # a 2^s scale, FP32 accumulation; beside it the FP32 path on the same values
+        # a 2^s scale, FP32 FIR accumulation, radix-16 DFT stages on FP16 matrix
+        # cores with FP32 accumulation. Beside it: the same int8/FP16 input with
+        # FP32 DFT stages, and the FP32 path on the same values.
         n, taps, n_samples = 4096, 16, 1 << 28
         m_total = n_samples // n - taps + 1
         x = signals.int8_input(n_samples, seed=signals.SEED_BASE + 3, sigma=16.0)
@@ -228,17 +233,24 @@ def main() -> int:
         del x
         h64 = signals.design_coeffs(n, taps, "hamming")
         h16, shift = signals.coeffs_fp16(h64)
-        ms8, used8 = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup,
-                               in_type=ppf.PPF_CI8, coeff_shift=shift)
-        rec = line("precision_n4096_t16_int8_fp16coef_2p28", n, taps, m_total, ms8, used8, args.steps,
+        msm, usedm = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup,
+                               in_type=ppf.PPF_CI8, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+        rec = line("precision_n4096_t16_int8_fp16coef_2p28", n, taps, m_total, msm, usedm, args.steps,
                    args.warmup, measured_traffic("c4"))
         in_b = metrics.input_bytes(n, m_total, 2)
-        rec["value"] = round(in_b / (ms8 * 1e-3) / 1e9, 3)
+        rec["value"] = round(in_b / (msm * 1e-3) / 1e9, 3)
         rec["realtime_multiple"] = round(metrics.realtime_multiple(rec["value"] * 1e9), 2)
-        rec["dtype"] = "ci8_in/f16_coef/f32_acc"
+        rec["dtype"] = "ci8_in/f16_coef/f32_fir/f16_mfma_f32_acc"
+        rec["config"]["fft"] = "mfma_f16_radix16"
         alg = metrics.algorithmic_bytes(n, taps, m_total, in_bytes=2, out_bytes=8, coeff_bytes=2)
-        rec["roofline"].update({"achieved": round(alg / (ms8 * 1e-3) / 1e9, 2), "algorithmic_bytes": alg})
+        rec["roofline"].update({"achieved": round(alg / (msm * 1e-3) / 1e9, 2), "algorithmic_bytes": alg})
         rec["roofline"]["frac"] = round(rec["roofline"]["achieved"] / rec["roofline"]["peak"], 4)
+        rec["samples_per_s"] = round(n * m_total / (msm * 1e-3), 1)
+        ms8, used8 = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup,
+                               in_type=ppf.PPF_CI8, coeff_shift=shift)
+        rec["int8_fp32_fft_path"] = {"ms_per_step": round(ms8, 5),
+                                     "input_gbps_int8": round(in_b / (ms8 * 1e-3) / 1e9, 3),
+                                     "path": {1: "fused", 2: "two_pass"}.get(used8)}
         x32 = torch.view_as_complex(x_dev.to(torch.float32).contiguous())
         del x_dev
         ms32, used32 = run_point(torch, n, taps, m_total, x32, h64.astype(np.float32), args.steps, args.warmup)
@@ -246,7 +258,6 @@ def main() -> int:
                                         "input_gbps_fp32": round(metrics.input_bytes(n, m_total) / (ms32 * 1e-3) / 1e9, 3),
                                         "samples_per_s": round(n * m_total / (ms32 * 1e-3), 1),
                                         "path": {1: "fused", 2: "two_pass"}.get(used32)}
-        rec["samples_per_s"] = round(n * m_total / (ms8 * 1e-3), 1)
         print(json.dumps(rec), flush=True)
         return 0
 

@@ -92,6 +92,9 @@ struct ppf_plan_s {
   float* d_coef = nullptr;
   float* d_ones = nullptr;
   void* d_tw = nullptr;
+  void* d_coef16 = nullptr;    // matrix-core mode: FP16 coefficients in lane order
+  void* d_dft16 = nullptr;     // matrix-core mode: FP16 DFT-16 values
+  int mfma_e1 = 0;             // matrix-core mode: samples are scaled by 2^-e1
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   long long chunk_spectra = 0;
@@ -108,11 +111,23 @@ struct ppf_plan_s {
     p.in_type = in_type == PPF_C32 ? 0 : (in_type == PPF_C16 ? 1 : 2);
     return p;
   }
+  ppf::MfmaDev mfma() const {
+    ppf::MfmaDev m;
+    m.coef16 = d_coef16;
+    m.tw = d_tw;
+    m.dft16 = d_dft16;
+    m.d = 16 - T;
+    m.in_scale = std::ldexp(1.0f, -mfma_e1);
+    m.out_scale = std::ldexp(1.0f, mfma_e1 - coeff_shift);
+    return m;
+  }
   ~ppf_plan_s() {
     if (d_coef) hipFree(d_coef);
     if (d_ones) hipFree(d_ones);
     if (d_tw) hipFree(d_tw);
     if (d_ws) hipFree(d_ws);
+    if (d_coef16) hipFree(d_coef16);
+    if (d_dft16) hipFree(d_dft16);
   }
 };
 
@@ -149,6 +164,12 @@ int ensure_workspace(ppf_plan_t p) {
 int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* out, long long M) {
   const ppf::PlanDev pd = p->dev();
   const size_t sb = (size_t)sample_bytes(p->in_type);
+  if (p->fft_mode == PPF_FFT_MFMA_F16) {
+    ppf::BatchArgs a{x0, x1, h0, out, M};
+    hipError_t e = ppf::launch_mfma(p->mfma(), a, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "matrix-core kernel launch");
+    return PPF_OK;
+  }
   if (p->path == PPF_PATH_FUSED) {
     ppf::BatchArgs a{x0, x1, h0, out, M};
     hipError_t e = ppf::launch_fused(pd, a, p->stream);
@@ -204,9 +225,13 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
     return nullptr;
   }
   if (coeff_shift < 0 || coeff_shift > 30) { fail(PPF_ERR_INVALID, "coeff_shift=%d outside 0..30", coeff_shift); return nullptr; }
-  if (fft_mode != PPF_FFT_F32) {
-    fail(PPF_ERR_UNSUPPORTED, "fft_mode=%d is not built for N=%d taps=%d", fft_mode, N, taps);
-    return nullptr;
+  if (fft_mode == PPF_FFT_MFMA_F16) {
+    if (!ppf::mfma_available(N, taps) || in_type != PPF_CI8 || coeff_type != PPF_R16) {
+      fail(PPF_ERR_UNSUPPORTED,
+           "fft_mode=MFMA_F16 takes N=4096, taps <= 16, complex int8 input and FP16 coefficients "
+           "(got N=%d taps=%d in_type=%d coeff_type=%d)", N, taps, in_type, coeff_type);
+      return nullptr;
+    }
   }
   if (!ppf::fft_available(N) || !ppf::fir_available(TP)) {
     fail(PPF_ERR_UNSUPPORTED, "no kernel for N=%d taps=%d", N, taps);
@@ -222,7 +247,7 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   p->coeff_type = coeff_type;
   p->coeff_shift = coeff_shift;
   p->fft_mode = fft_mode;
-  p->path = fused_ok_for(N, TP, in_type) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+  p->path = (fft_mode == PPF_FFT_MFMA_F16 || fused_ok_for(N, TP, in_type)) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
 
   // coefficients padded at the front with TP-T zero segments; FP16
   // coefficients are widened exactly and the 2^-shift is applied (exact)
@@ -243,6 +268,28 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   if ((e = hipMemcpy(p->d_coef, hpad.data(), hpad.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
   if ((e = hipMemcpy(p->d_ones, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
   if ((e = ppf::launch_twiddles(p->d_tw, N, nullptr)) != hipSuccess) goto hip_fail;
+  if (fft_mode == PPF_FFT_MFMA_F16) {
+    // FP16 coefficients in the kernel's lane order, and the sample scale:
+    // the largest FP16 stage input is at most 128 * 256 * S * 2^-e1 with
+    // S = max over channels of sum_t |h16[t][c]| (|x| <= 128 for int8 and
+    // two radix-16 stages of growth <= 16 each); e1 keeps it below 60000.
+    const uint16_t* h16 = (const uint16_t*)coeffs;
+    std::vector<uint16_t> lane(ppf::mfma_coef_bytes() / 2);
+    ppf::mfma_coef_layout(h16, taps, lane.data());
+    double smax = 0.0;
+    for (int c = 0; c < N; ++c) {
+      double sc = 0.0;
+      for (int t = 0; t < taps; ++t) sc += std::fabs((double)half_to_float(h16[(size_t)t * N + c]));
+      smax = sc > smax ? sc : smax;
+    }
+    int e1 = smax > 0.0 ? (int)std::ceil(std::log2(128.0 * 256.0 * smax / 60000.0)) : 0;
+    e1 = e1 < -8 ? -8 : (e1 > 24 ? 24 : e1);
+    p->mfma_e1 = e1;
+    if ((e = hipMalloc(&p->d_coef16, lane.size() * 2)) != hipSuccess) { p->d_coef16 = nullptr; goto hip_fail; }
+    if ((e = hipMalloc(&p->d_dft16, 64)) != hipSuccess) { p->d_dft16 = nullptr; goto hip_fail; }
+    if ((e = hipMemcpy(p->d_coef16, lane.data(), lane.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
+    if ((e = ppf::launch_dft16(p->d_dft16, nullptr)) != hipSuccess) goto hip_fail;
+  }
   if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) goto hip_fail;
   g_status = PPF_OK;
   return p;
@@ -293,14 +340,17 @@ int ppf_plan_set_path(ppf_plan_t plan, int path) {
   if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
   switch (path) {
     case PPF_PATH_AUTO:
-      plan->path = fused_ok_for(plan->N, plan->TP, plan->in_type) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+      plan->path = (plan->fft_mode == PPF_FFT_MFMA_F16 || fused_ok_for(plan->N, plan->TP, plan->in_type))
+                       ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
       return PPF_OK;
     case PPF_PATH_FUSED:
-      if (!fused_ok_for(plan->N, plan->TP, plan->in_type))
+      if (plan->fft_mode != PPF_FFT_MFMA_F16 && !fused_ok_for(plan->N, plan->TP, plan->in_type))
         return fail(PPF_ERR_UNSUPPORTED, "no fused kernel for N=%d taps=%d", plan->N, plan->T);
       plan->path = PPF_PATH_FUSED;
       return PPF_OK;
     case PPF_PATH_TWO_PASS:
+      if (plan->fft_mode == PPF_FFT_MFMA_F16)
+        return fail(PPF_ERR_UNSUPPORTED, "the matrix-core mode has only the fused path");
       plan->path = PPF_PATH_TWO_PASS;
       return PPF_OK;
     default:
@@ -319,7 +369,9 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value) {
     case PPF_Q_IN_TYPE: *value = plan->in_type; return PPF_OK;
     case PPF_Q_FFT_MODE: *value = plan->fft_mode; return PPF_OK;
     case PPF_Q_COEFF_SHIFT: *value = plan->coeff_shift; return PPF_OK;
-    case PPF_Q_FUSED_AVAILABLE: *value = fused_ok_for(plan->N, plan->TP, plan->in_type) ? 1 : 0; return PPF_OK;
+    case PPF_Q_FUSED_AVAILABLE:
+      *value = (plan->fft_mode == PPF_FFT_MFMA_F16 || fused_ok_for(plan->N, plan->TP, plan->in_type)) ? 1 : 0;
+      return PPF_OK;
     default: return fail(PPF_ERR_INVALID, "query key %d unknown", key);
   }
 }

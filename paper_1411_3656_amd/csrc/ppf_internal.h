@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI layer (ppf_api.cpp) and the HIP
-// kernels (ppf_kernels.hip). Not installed; not part of the ABI.
+// kernels (ppf_kernels.hip, ppf_mfma.hip). Not installed; not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,6 +84,22 @@ hipError_t launch_twiddles(void* tw, int N, hipStream_t st);
 hipError_t launch_history(const void* old_hist, const void* chunk, void* new_hist,
                           long long hist_samples, long long chunk_samples, int sample_bytes,
                           hipStream_t st);
+
+// Reduced-precision fused kernel with matrix-core DFT stages (N = 4096,
+// complex int8 input, FP16 coefficients).
+struct MfmaDev {
+  const void* coef16;  // 16 tap slots x 4096 FP16 coefficients in lane order
+  const void* tw;      // 4096 complex FP32 twiddles
+  const void* dft16;   // 16 complex FP16 values exp(-2 pi i k/16)
+  int d;               // leading zero tap slots (16 - T)
+  float in_scale;      // 2^-e1 applied to the int8 samples (exact in FP16)
+  float out_scale;     // 2^(e1 - coeff_shift) applied to the FP32 spectra
+};
+bool mfma_available(int N, int TP);
+size_t mfma_coef_bytes();
+void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst);
+hipError_t launch_dft16(void* table, hipStream_t st);
+hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st);
 
 }  // namespace ppf
 

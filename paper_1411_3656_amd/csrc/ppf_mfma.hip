@@ -1,0 +1,456 @@
+// Fused reduced-precision PPF kernel for N = 4096 = 16^3 channels and up to
+// 16 taps on CDNA4 (gfx950): complex int8 input, FP16 coefficients, FP32
+// FIR accumulation, and the 4096-point DFT as three radix-16 stages whose
+// 16-point DFTs run on the matrix cores (v_mfma_f32_16x16x32_f16: FP16
+// operands, FP32 accumulation) with FP32 twiddle multiplies in between.
+//
+// What is computed (section 2, Eq. 1 per channel, then the DFT of section 3):
+//   u[m][c] = sum_t h[t][c] x[m+t][c],   X[m][k] = sum_c u[m][c] W^(c k),
+// W = exp(-2 pi i / 4096). With c = c0 + 256 p (c0 = a + 16 b) and
+// k = k1 + 16 k2 + 256 k3 the DFT factors as
+//   X = sum_a W16^(a k3) W256^(a k2) sum_b W16^(b k2) W^(c0 k1) sum_p W16^(p k1) u[c0 + 256 p],
+// i.e. stage 1 (16-point DFTs over p), twiddle W^(c0 k1), stage 2 (over b),
+// twiddle W256^(a k2), stage 3 (over a).
+//
+// One workgroup of 1024 threads (16 waves) owns a tile of consecutive
+// spectra. A 16-point complex DFT of 16 vectors is two MFMAs: the DFT
+// matrix as the 16x32 real A operand ([Re F, -Im F] and [Im F, Re F] rows
+// over interleaved (re, im) inputs) and the 16 vectors as the 32x16 B
+// operand. Lane l of wave w supplies points 4h..4h+3 (h = l / 16) of
+// vector l % 16 and receives outputs 4h..4h+3 of that vector.
+//
+// The FIR lane layout is the stage-1 operand layout: lane (w, j, h) owns
+// channels c0 + 256 (4h + e), c0 = 16 w + j, e < 4, so its presums are
+// exactly its B operand and need no exchange. Each lane keeps a ring of
+// the last 16 input blocks of its 4 channels as packed FP16 (re, im) in
+// registers (int8 values, pre-scaled by a power of two, are exact in FP16);
+// the coefficients of all taps live in LDS in lane order. The spectrum loop
+// is unrolled by the ring size so ring slots are static registers.
+// Stage outputs are exchanged through two swizzled LDS buffers of FP16
+// complex values; two barriers per spectrum.
+//
+// Scaling: the ring holds x * 2^-e1 and the FIR uses the FP16 coefficients
+// h16 = h * 2^s as given, so stage inputs are 2^(s-e1) times the true
+// values; e1 is chosen on the host so that no FP16 stage input can
+// overflow for any int8 input, and the output is multiplied by 2^(e1-s).
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppf_internal.h"
+
+namespace ppf {
+namespace {
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+constexpr int kN = 4096;
+constexpr int kTaps = 16;                       // ring size and coefficient slots
+constexpr int kThreads = 1024;
+constexpr int kCoefBytes = kTaps * kN * 2;      // FP16 coefficients in LDS
+constexpr int kXchgBytes = kN * 4;              // one FP16 complex exchange buffer
+constexpr int kLdsBytes = kCoefBytes + 2 * kXchgBytes;
+#ifndef PPF_MFMA_TW_REGS
+#define PPF_MFMA_TW_REGS 1
+#endif
+#ifndef PPF_MFMA_COEF_GROUP
+#define PPF_MFMA_COEF_GROUP 2
+#endif
+constexpr int kCoefGroup = PPF_MFMA_COEF_GROUP;   // taps per batch of coefficient reads
+
+constexpr int kBufDword3 = 0x00020000;
+constexpr int kAuxNt = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kBufDword3);
+}
+
+// Exchange-buffer swizzle in 4-byte element units: XOR element bits 2-3
+// with bits 6-7 and bits 4-5 with bits 10-11. Bits 0-1 are kept, so the
+// four points a lane reads stay one aligned 16-byte group.
+__device__ __forceinline__ constexpr int swz(int e) {
+  return e ^ (((e >> 6) & 3) << 2) ^ (((e >> 10) & 3) << 4);
+}
+
+__device__ __forceinline__ uint32_t pack_h2(float re, float im) {
+  h2 v;
+  v.x = (_Float16)re;
+  v.y = (_Float16)im;
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// One complex int8 sample (bytes re, im in the low half of raw) to a packed
+// FP16 (re, im) pair scaled by sc = 2^-e1, exactly: with the sign bit
+// flipped, byte b becomes the FP16 number 1024 + b + 128 when 0x64 is placed
+// above it, and sc * (that - 1152) = sc * x is representable.
+__device__ __forceinline__ uint32_t widen1(uint32_t raw, h2 sc, h2 bias) {
+  const uint32_t t = __builtin_amdgcn_perm(0x64646464u, raw ^ 0x8080u, 0x04010400u);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(__builtin_bit_cast(h2, t), sc, bias));
+}
+
+}  // namespace
+
+struct MfmaParams {
+  const void* x0;            // complex int8, first segment (h0 blocks)
+  const void* x1;            // complex int8, second segment
+  v2f* out;                  // complex FP32 spectra
+  const uint4* coef;         // [16][4096] FP16 coefficients in lane order
+  const v2f* tw;             // 4096 FP32 twiddles exp(-2 pi i k / 4096)
+  const uint32_t* dft16;     // 16 FP16 complex exp(-2 pi i k / 16), (re, im) packed
+  int h0;
+  int M;                     // spectra
+  int S;                     // spectra per tile
+  int d;                     // leading zero tap slots (16 - T)
+  int nblocks;
+  float in_scale;            // 2^-e1
+  float out_scale;           // 2^(e1 - s)
+};
+
+namespace {
+
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int q = nblocks >> 3, rem = nblocks & 7;
+  const int xcd = bid & 7, k = bid >> 3;
+  return xcd * q + (xcd < rem ? xcd : rem) + k;
+}
+
+template <int PF, int AUX>
+struct MfmaEngine {
+  static_assert(kTaps % PF == 0, "prefetch depth divides the ring");
+  const MfmaParams& p;
+  uint8_t* lds;
+  int w, j, h, tid;
+  int m0, ng;
+  int vb_lo, vb_hi;
+  uint32_t in_off;           // lane byte offset in an input block (channel 16w+j+1024h)
+  uint32_t out_off;          // lane byte offset in an output spectrum
+  uint32_t wr1, wr2, rd;     // swizzled exchange byte offsets (r = 0 terms)
+  h8 a_re;                   // DFT-16 matrix row of this lane (real parts of the outputs)
+#if PPF_MFMA_TW_REGS
+  v2f tw1[4], tw2[4];        // stage twiddles of this lane's outputs
+#else
+  int tw1i, tw1s, tw2i;      // twiddle indices of output r: tw1i + r*tw1s, tw2i + r*16j (mod N)
+#endif
+  h2 sc, bias;
+
+  __device__ __forceinline__ MfmaEngine(const MfmaParams& p_, uint8_t* lds_) : p(p_), lds(lds_) {}
+
+  __device__ __forceinline__ const uint8_t* block_ptr(int rb) const {
+    return rb < p.h0 ? (const uint8_t*)p.x0 + (size_t)rb * kN * 2
+                     : (const uint8_t*)p.x1 + (size_t)(rb - p.h0) * kN * 2;
+  }
+
+  // raw int8 pairs of this lane's 4 channels of virtual block vb, one per
+  // register (zero-extended 16-bit loads; combining them here would make the
+  // step wait for its own prefetch). A block outside [vb_lo, vb_hi) (zero
+  // padding, or beyond what the tile uses) gets an empty buffer range, so
+  // its loads return zero without touching memory; no branch either.
+  __device__ __forceinline__ void load(uint32_t (&dst)[4], int vb) const {
+    const bool in = vb >= vb_lo && vb < vb_hi;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(in ? block_ptr(vb - p.d) : p.x1, in ? kN * 2 : 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, in_off, 512 * e, AUX);
+  }
+
+  __device__ __forceinline__ void widen(const uint32_t (&raw)[4], uint32_t (&slot)[4]) const {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) slot[e] = widen1(raw[e], sc, bias);
+  }
+
+  __device__ __forceinline__ void init(int lb) {
+    tid = threadIdx.x;
+    w = tid >> 6;
+    j = tid & 15;
+    h = (tid >> 4) & 3;
+    m0 = lb * p.S;
+    const int rem = p.M - m0;
+    ng = rem < p.S ? rem : p.S;
+    vb_lo = m0 > p.d ? m0 : p.d;
+    vb_hi = m0 + ng + kTaps - 1;
+    in_off = (uint32_t)(16 * w + j + 1024 * h) * 2u;
+    out_off = (uint32_t)(j + 16 * w + 1024 * h) * 8u;
+    wr1 = kCoefBytes + swz(1024 * h + 16 * j + w) * 4;                 // in X
+    wr2 = kCoefBytes + kXchgBytes + swz(1024 * h + 16 * w + j) * 4;    // in Y
+    rd = swz(256 * w + 16 * j + 4 * h) * 4;
+    const _Float16 s16 = (_Float16)p.in_scale;
+    sc = h2{s16, s16};
+    const _Float16 b16 = (_Float16)(-1152.0f * p.in_scale);
+    bias = h2{b16, b16};
+
+    // coefficients into LDS (lane order: tap t, lane tid -> 8 bytes)
+#pragma unroll
+    for (int i = 0; i < kCoefBytes / 16 / kThreads; ++i)
+      ((uint4*)lds)[tid + i * kThreads] = p.coef[tid + i * kThreads];
+
+    // A operand: row j of the DFT-16 matrix for real outputs, inputs
+    // (p, re/im) for p = 4h + e: (wr, -wi) with W16^(p j) = wr + i wi
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const h2 wv = __builtin_bit_cast(h2, p.dft16[((4 * h + e) * j) & 15]);
+      a_re[2 * e] = wv.x;
+      a_re[2 * e + 1] = -wv.y;
+    }
+#if PPF_MFMA_TW_REGS
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tw1[r] = p.tw[((16 * w + j) * (4 * h + r)) & (kN - 1)];
+      tw2[r] = p.tw[(16 * j * (4 * h + r)) & (kN - 1)];
+    }
+#else
+    tw1i = ((16 * w + j) * 4 * h) & (kN - 1);
+    tw1s = 16 * w + j;
+    tw2i = (16 * j * 4 * h) & (kN - 1);
+#endif
+  }
+
+  // twiddles of this lane's 4 outputs: index i0 + r*step (mod N), read from
+  // the FP32 table (32 KiB, stays in the vector L1/L2)
+  __device__ __forceinline__ void twiddles(int i0, int step, v2f (&tw)[4]) const {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tw[r] = p.tw[(i0 + r * step) & (kN - 1)];
+  }
+
+  // Re X = A_re . (xr, xi) and Im X = A_re . (xi, -xr): the -i rotation of
+  // the inputs replaces a second matrix (one packed multiply per register)
+  __device__ __forceinline__ void dft16(const h8& b, f4& dre, f4& dim) const {
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    dre = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_re, b, z, 0, 0, 0);
+    h8 bi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bi[2 * e] = b[2 * e + 1];
+      bi[2 * e + 1] = -b[2 * e];
+    }
+    dim = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_re, bi, z, 0, 0, 0);
+  }
+
+  // twiddle in FP32, round to FP16, scatter to the next stage's layout
+  __device__ __forceinline__ void twiddle_store(const f4& dre, const f4& dim, const v2f (&tw)[4], uint32_t base) const {
+    // a fresh base per use: the four stores then take immediate offsets
+    // instead of four loop-invariant address registers
+    asm volatile("" : "+v"(base));
+    uint32_t* dst = (uint32_t*)(lds + base);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float yr = fmaf(dre[r], tw[r].x, -dim[r] * tw[r].y);
+      const float yi = fmaf(dre[r], tw[r].y, dim[r] * tw[r].x);
+      dst[256 * r] = pack_h2(yr, yi);
+    }
+  }
+
+  __device__ __forceinline__ h8 read_vec(int buf) const {
+    return __builtin_bit_cast(h8, *(const uint4*)(lds + buf + rd));
+  }
+
+  __device__ __forceinline__ void run() {
+    constexpr int X = kCoefBytes, Y = kCoefBytes + kXchgBytes;
+
+    uint32_t ring[kTaps][4];
+    uint32_t stage[PF][4];
+#pragma unroll
+    for (int s = 0; s < kTaps; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ring[s][e] = 0u;
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) stage[s][e] = 0u;
+
+    // blocks 0 .. 14 into ring slots 0 .. 14; loads of 15 .. 14+PF in flight
+#pragma unroll
+    for (int s = 0; s < kTaps - 1; ++s) {
+      uint32_t raw[4];
+      load(raw, m0 + s);   // zero (which widens to 0.0) outside the read range
+      widen(raw, ring[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < PF; ++s) load(stage[s], m0 + kTaps - 1 + s);
+    __syncthreads();   // coefficients in LDS
+
+    for (int base = 0; base < ng; base += kTaps) {
+#pragma unroll
+      for (int k = 0; k < kTaps; ++k) {
+        const int it = base + k;
+        if (it < ng) {   // uniform over the block; keeps the loop fully unrolled
+        // block it+15 into the slot of block it-1; refill its staging slot
+        widen(stage[k % PF], ring[(k + kTaps - 1) % kTaps]);
+        load(stage[k % PF], m0 + it + kTaps - 1 + PF);
+
+        // each step widens the ring values itself (in the FMA) instead of
+        // keeping FP32 copies alive across steps
+#pragma unroll
+        for (int s = 0; s < kTaps; ++s)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(ring[s][e]));
+        // FIR: taps t = 0 .. 15 over ring slots (k + t) % 16, FP32 sums
+        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+          // coefficient reads issued a few taps ahead, not all at once
+          if (t % kCoefGroup == 0) __builtin_amdgcn_sched_barrier(0);
+          const h4 hv = *(const h4*)(lds + t * (kN * 2) + tid * 8);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const h2 xv = __builtin_bit_cast(h2, ring[(k + t) % kTaps][e]);
+            ar[e] = fmaf((float)hv[e], (float)xv.x, ar[e]);
+            ai[e] = fmaf((float)hv[e], (float)xv.y, ai[e]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        h8 b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          b[2 * e] = (_Float16)ar[e];
+          b[2 * e + 1] = (_Float16)ai[e];
+        }
+
+#if PPF_MFMA_TW_REGS
+        f4 dre, dim;
+        dft16(b, dre, dim);                       // stage 1 over p
+        twiddle_store(dre, dim, tw1, wr1);        // W^(c0 k1), to stage-2 layout (X)
+        __syncthreads();
+        dft16(read_vec(X), dre, dim);             // stage 2 over b
+        twiddle_store(dre, dim, tw2, wr2);        // W256^(a k2), to stage-3 layout (Y)
+#else
+        v2f tw[4];
+        twiddles(tw1i, tw1s, tw);
+        f4 dre, dim;
+        dft16(b, dre, dim);                       // stage 1 over p
+        twiddle_store(dre, dim, tw, wr1);         // W^(c0 k1), to stage-2 layout (X)
+        twiddles(tw2i, 16 * j, tw);
+        __syncthreads();
+        dft16(read_vec(X), dre, dim);             // stage 2 over b
+        twiddle_store(dre, dim, tw, wr2);         // W256^(a k2), to stage-3 layout (Y)
+#endif
+        __syncthreads();
+        dft16(read_vec(Y), dre, dim);             // stage 3 over a
+
+        const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * kN, kN * 8);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v2f o;
+          o.x = dre[r] * p.out_scale;
+          o.y = dim[r] * p.out_scale;
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, o),
+                                                rs, out_off, (uint32_t)(2048 * r), kAuxNt);
+        }
+        }
+      }
+    }
+  }
+};
+
+template <int PF, int AUX>
+__global__ void __launch_bounds__(kThreads) ppf_mfma_kernel(MfmaParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds_mfma[];
+  const int lb = xcd_tile(blockIdx.x, p.nblocks);
+  if (lb * p.S >= p.M) return;    // whole block idle
+  MfmaEngine<PF, AUX> eng(p, lds_mfma);
+  eng.init(lb);
+  eng.run();
+}
+
+__global__ void ppf_dft16_kernel(uint32_t* t) {
+  const int k = threadIdx.x;
+  if (k < 16) {
+    double s, c;
+    sincospi(-2.0 * (double)k / 16.0, &s, &c);   // exact angle, rounded once to FP16
+    h2 v;
+    v.x = (_Float16)c;
+    v.y = (_Float16)s;
+    t[k] = __builtin_bit_cast(uint32_t, v);
+  }
+}
+
+#ifndef PPF_MFMA_PF
+#define PPF_MFMA_PF 1
+#endif
+#ifndef PPF_MFMA_NT
+#define PPF_MFMA_NT 0
+#endif
+using MfmaKernel = void (*)(MfmaParams);
+constexpr MfmaKernel kMfmaKernel = ppf_mfma_kernel<PPF_MFMA_PF, PPF_MFMA_NT ? kAuxNt : 0>;
+
+int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+  }
+  return n;
+}
+
+}  // namespace
+
+bool mfma_available(int N, int TP) { return N == kN && TP <= kTaps; }
+
+size_t mfma_coef_bytes() { return (size_t)kCoefBytes; }
+
+// FP16 coefficients h16[t*N + c] (T taps) -> lane-order table of 16 slots,
+// the first 16-T zero: slot t, thread tid, element e holds the coefficient
+// of channel 16*(tid/64) + tid%16 + 1024*((tid/16)%4) + 256*e.
+void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst) {
+  const int d = kTaps - T;
+  for (int t = 0; t < kTaps; ++t)
+    for (int tid = 0; tid < kThreads; ++tid)
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * (tid >> 6) + (tid & 15) + 1024 * ((tid >> 4) & 3) + 256 * e;
+        dst[(size_t)t * kN + tid * 4 + e] = t < d ? (uint16_t)0 : h16[(size_t)(t - d) * kN + c];
+      }
+}
+
+hipError_t launch_dft16(void* table, hipStream_t st) {
+  hipLaunchKernelGGL(ppf_dft16_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)table);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st) {
+  if (a.M <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)kMfmaKernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  // one workgroup per CU (the LDS holds a single one); split larger
+  // batches into launches whose spectrum indices fit in 32 bits
+  const long long kMaxLaunch = 1ll << 28;
+  for (long long s0 = 0; s0 < a.M; s0 += kMaxLaunch) {
+    const long long k = a.M - s0 < kMaxLaunch ? a.M - s0 : kMaxLaunch;
+    MfmaParams p;
+    if (s0 < a.h0) {
+      p.x0 = (const uint8_t*)a.x0 + (size_t)s0 * kN * 2;
+      p.h0 = (int)(a.h0 - s0);
+      p.x1 = a.x1;
+    } else {
+      p.x0 = a.x1;
+      p.h0 = 0;
+      p.x1 = (const uint8_t*)a.x1 + (size_t)(s0 - a.h0) * kN * 2;
+    }
+    p.out = (v2f*)a.out + (size_t)s0 * kN;
+    p.coef = (const uint4*)md.coef16;
+    p.tw = (const v2f*)md.tw;
+    p.dft16 = (const uint32_t*)md.dft16;
+    p.M = (int)k;
+    const int cus = cu_count();
+    int S = (int)((k + cus - 1) / cus);
+    if (S < 1) S = 1;
+    p.S = S;
+    p.nblocks = (int)((k + S - 1) / S);
+    p.d = md.d;
+    p.in_scale = md.in_scale;
+    p.out_scale = md.out_scale;
+    hipLaunchKernelGGL(kMfmaKernel, dim3(p.nblocks), dim3(kThreads), kLdsBytes, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ppf

@@ -77,7 +77,7 @@ def main(argv=None):
     w_scale = a.copy_bytes / (cwrite * 1024)
     read_b = fetch * 1024 * f_scale
     write_b = write * 1024 * w_scale
-    rec = {"workload": a.workload, "kernel": a.kernel, "kernel_hash": bench.kernel_hash(),
+    rec = {"workload": a.workload, "kernel": a.kernel, "kernel_hash": bench.kernel_hash(a.workload),
            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
            "copy_fetch_kib": cfetch, "copy_write_kib": cwrite, "copy_bytes": a.copy_bytes,
            "fetch_scale": f_scale, "write_scale": w_scale,

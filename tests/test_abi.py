@@ -84,6 +84,27 @@ def test_plan_ex_validates_types():
     assert ppf.last_error()[0] == ppf.PPF_ERR_INVALID
 
 
+def test_matrix_core_mode_validates_its_domain():
+    """The FP16 matrix-core mode is built for N=4096 = 16^3, taps <= 16,
+    complex int8 input and FP16 coefficients; anything else is rejected
+    before any device call."""
+    L = ppf.lib()
+    h16 = np.ones(4096 * 16, dtype=np.float16)
+    h32 = np.ones(4096 * 16, dtype=np.float32)
+    mf = ppf.PPF_FFT_MFMA_F16
+    cases = [
+        (1024, 16, h16, ppf.PPF_R16, ppf.PPF_CI8),     # N is not 16^3
+        (4096, 17, np.ones(4096 * 17, np.float16), ppf.PPF_R16, ppf.PPF_CI8),   # more than 16 taps
+        (4096, 16, h32, ppf.PPF_R32, ppf.PPF_CI8),     # FP32 coefficients
+        (4096, 16, h16, ppf.PPF_R16, ppf.PPF_C16),     # FP16 input (no range bound)
+        (4096, 16, h16, ppf.PPF_R16, ppf.PPF_C32),
+    ]
+    for n, taps, h, ct, it in cases:
+        assert not L.ppf_plan_ex(n, taps, h.ctypes.data, ct, 0, it, mf)
+        code, msg = ppf.last_error()
+        assert code == ppf.PPF_ERR_UNSUPPORTED and "MFMA" in msg, (n, taps, ct, it, msg)
+
+
 def test_null_handles():
     L = ppf.lib()
     assert L.ppf_execute(None, None, None, 4) == ppf.PPF_ERR_INVALID

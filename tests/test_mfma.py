@@ -1,0 +1,138 @@
+"""Matrix-core reduced-precision form on the GPU (N = 4096 = 16^3, taps <= 16,
+complex int8 input, FP16 coefficients): FIR in FP32 from exact FP16
+operands, then three radix-16 DFT stages on FP16 MFMA with FP32
+accumulation and FP32 twiddles, stage inputs rounded to FP16.
+
+Parity is against the FP64 oracle fed the identical int8 samples and the
+FP16 coefficients exactly as stored (times 2^-shift). The arithmetic rounds
+each of the three stage inputs and the DFT-16 matrix entries to FP16 (unit
+roundoff u = 2^-11); an RMS relative error of about u per rounding point
+puts the expected SNR near 68 dB. The bar is SNR >= 62 dB and a largest
+error of at most 8e-3 of the output RMS.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_3656_amd import ppf, signals
+
+pytestmark = pytest.mark.gpu
+N = 4096
+MIN_SNR_DB = 62.0
+MAX_ERR_OVER_RMS = 8e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def snr_db(got, ref):
+    return float(10.0 * np.log10(np.sum(np.abs(ref) ** 2) / np.sum(np.abs(got - ref) ** 2)))
+
+
+def rel_err(got, ref):
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    return float(np.max(np.abs(got - ref))) / rms
+
+
+def fp16_coeffs(taps, kind="hamming"):
+    h16, shift = signals.coeffs_fp16(signals.design_coeffs(N, taps, kind))
+    return h16, shift, h16.astype(np.float64) * 2.0 ** -shift
+
+
+def mfma_plan(h16, taps, shift):
+    return ppf.Plan(N, taps, h16, in_type=ppf.PPF_CI8, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+
+
+def check(got, ref, label):
+    s, e = snr_db(got, ref), rel_err(got, ref)
+    print(f"  {label}: SNR {s:.1f} dB, max err/rms {e:.2e}", flush=True)
+    assert s >= MIN_SNR_DB, (label, s)
+    assert e <= MAX_ERR_OVER_RMS, (label, e)
+
+
+@pytest.mark.parametrize("taps,m_total", [(16, 1), (16, 37), (16, 300), (9, 37), (1, 20)])
+def test_matches_oracle(taps, m_total):
+    torch = _torch()
+    print(f"case mfma N={N} T={taps} M={m_total}", flush=True)
+    h16, shift, h_exact = fp16_coeffs(taps)
+    x = signals.int8_input((m_total + taps - 1) * N, seed=700 + taps + m_total, sigma=16.0)
+    plan = mfma_plan(h16, taps, shift)
+    assert plan.path == ppf.PPF_PATH_FUSED
+    got = plan.execute(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    plan.close()
+    pick = list(range(m_total)) if m_total <= 40 else sorted(set(range(0, m_total, 7)) | {1, 2, m_total - 2, m_total - 1})
+    ref = oracle.ppf(x, h_exact, N, taps, spectra=pick)
+    assert np.all(np.isfinite(got))
+    check(got[pick], ref, f"T={taps} M={m_total}")
+
+
+def test_long_tiles_sampled():
+    """More spectra per workgroup tile than the 16-step unrolled loop
+    (4500 spectra over at most 256 tiles), sampled at tile edges."""
+    torch = _torch()
+    taps, m_total = 16, 4500
+    print(f"case mfma long tiles M={m_total}", flush=True)
+    h16, shift, h_exact = fp16_coeffs(taps)
+    x = signals.int8_input((m_total + taps - 1) * N, seed=77, sigma=16.0)
+    plan = mfma_plan(h16, taps, shift)
+    got = plan.execute(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    plan.close()
+    s = -(-m_total // 256)
+    edges = {e for k in range(1, 256) for e in (k * s - 1, k * s) if k * s < m_total}
+    pick = sorted(set(range(0, m_total, 97)) | set(range(0, m_total, 61)) | set(list(edges)[:40])
+                  | {0, 15, 16, 17, m_total - 1})
+    ref = oracle.ppf(x, h_exact, N, taps, spectra=pick)
+    check(got[pick].cpu().numpy(), ref, "long tiles")
+
+
+def test_stream_chunks_match_oracle_stream():
+    torch = _torch()
+    taps = 16
+    h16, shift, h_exact = fp16_coeffs(taps)
+    lens = [3, 1, 17, 2, 20]
+    x = signals.int8_input(sum(lens) * N, seed=91, sigma=16.0)
+    plan = mfma_plan(h16, taps, shift)
+    ppf.ppf_set_stream(plan.handle, torch.cuda.current_stream().cuda_stream)
+    st = ppf.ppf_stream_create(plan.handle)
+    chunks, outs, at = [], [], 0
+    for s in lens:
+        c = x[at * N:(at + s) * N]
+        chunks.append(c)
+        xd = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+        od = torch.empty((s, N), dtype=torch.complex64, device="cuda")
+        ppf.ppf_stream_push(st, xd, od, s)
+        outs.append((xd, od))
+        at += s
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy() for _, o in outs])
+    ref = np.concatenate(oracle.ppf_stream(chunks, h_exact, N, taps))
+    check(got, ref, "stream")
+    ppf.ppf_stream_destroy(st)
+    plan.close()
+
+
+def test_deterministic_and_path_fixed():
+    torch = _torch()
+    taps = 16
+    h16, shift, _ = fp16_coeffs(taps)
+    x = torch.from_numpy(signals.int8_input((40 + taps - 1) * N, seed=5, sigma=16.0)).cuda()
+    plan = mfma_plan(h16, taps, shift)
+    a = plan.execute(x)
+    b = plan.execute(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(ppf.PPFError) as ei:
+        ppf.ppf_plan_set_path(plan.handle, ppf.PPF_PATH_TWO_PASS)
+    assert ei.value.status == ppf.PPF_ERR_UNSUPPORTED
+    assert ppf.ppf_plan_query(plan.handle, ppf.PPF_Q_FFT_MODE) == ppf.PPF_FFT_MFMA_F16
+    plan.close()

@@ -111,7 +111,8 @@ def test_int8_stream_split_matches_oracle():
 
 
 def test_c4_precision_form_full_size_sampled():
-    """N=4096, T=16, 2^28 complex int8 samples (sigma 16), FP16 sinc x Hamming."""
+    """N=4096, T=16, 2^28 complex int8 samples (sigma 16), FP16 sinc x Hamming:
+    FP32 DFT stages and FP16 matrix-core DFT stages, and the FP32 path."""
     torch = _torch()
     n, taps, n_samples = 4096, 16, 1 << 28
     m_total = oracle.n_spectra(n_samples, n, taps)
@@ -124,6 +125,11 @@ def test_c4_precision_form_full_size_sampled():
     got = plan.execute(xd)
     torch.cuda.synchronize()
     plan.close()
+    # the same inputs with the radix-16 DFT stages on FP16 matrix cores
+    plan_m = ppf.Plan(n, taps, h16, in_type=ppf.PPF_CI8, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+    got_m = plan_m.execute(xd)
+    torch.cuda.synchronize()
+    plan_m.close()
     # the FP32 path on the same values (int8 widened, FP32 coefficients)
     x32 = torch.view_as_complex(xd.to(torch.float32).contiguous())
     plan32 = ppf.Plan(n, taps, h64.astype(np.float32))
@@ -133,6 +139,7 @@ def test_c4_precision_form_full_size_sampled():
     pick = sorted(set(range(0, m_total, 97)) | set(range(2 * taps)) | set(range(m_total - 2 * taps, m_total)))
     g = got[pick].cpu().numpy()
     g32 = got32[pick].cpu().numpy()
+    gm = got_m[pick].cpu().numpy()
     ref = oracle.ppf(x, h_exact, n, taps, spectra=pick)
     ref64 = oracle.ppf(x, h64, n, taps, spectra=pick)
     err = rel_err(g, ref)
@@ -140,6 +147,8 @@ def test_c4_precision_form_full_size_sampled():
         "workload": "precision_n4096_t16_int8_2p28", "spectra_checked": len(pick),
         "int8_fp16coef": {"arith_max_err_over_rms": err, "arith_snr_db": float(snr_db(g, ref)),
                           "e2e_snr_db": float(snr_db(g, ref64)), "e2e_max_err_over_rms": rel_err(g, ref64)},
+        "int8_fp16coef_mfma_f16": {"arith_max_err_over_rms": rel_err(gm, ref), "arith_snr_db": float(snr_db(gm, ref)),
+                                   "e2e_snr_db": float(snr_db(gm, ref64)), "e2e_max_err_over_rms": rel_err(gm, ref64)},
         "fp32_path": {"e2e_snr_db": float(snr_db(g32, ref64)), "e2e_max_err_over_rms": rel_err(g32, ref64)},
     }
     print(json.dumps(report))
@@ -149,3 +158,5 @@ def test_c4_precision_form_full_size_sampled():
             json.dump(report, f, indent=1)
     assert err <= TOL
     assert rel_err(g32, ref64) <= TOL
+    # matrix-core DFT stages: FP16 rounding bar (derivation in test_mfma)
+    assert snr_db(gm, ref) >= 62.0 and rel_err(gm, ref) <= 8e-3
