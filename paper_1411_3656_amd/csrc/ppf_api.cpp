@@ -93,7 +93,7 @@ struct ppf_plan_s {
   float* d_ones = nullptr;
   void* d_tw = nullptr;
   void* d_coef16 = nullptr;    // matrix-core mode: FP16 coefficients in lane order
-  void* d_dft16 = nullptr;     // matrix-core mode: FP16 DFT-16 values
+  void* d_w256 = nullptr;      // matrix-core mode: FP16 values exp(-2 pi i k/256)
   int mfma_e1 = 0;             // matrix-core mode: samples are scaled by 2^-e1
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -115,7 +115,7 @@ struct ppf_plan_s {
     ppf::MfmaDev m;
     m.coef16 = d_coef16;
     m.tw = d_tw;
-    m.dft16 = d_dft16;
+    m.w256 = d_w256;
     m.d = 16 - T;
     m.in_scale = std::ldexp(1.0f, -mfma_e1);
     m.out_scale = std::ldexp(1.0f, mfma_e1 - coeff_shift);
@@ -127,7 +127,7 @@ struct ppf_plan_s {
     if (d_tw) hipFree(d_tw);
     if (d_ws) hipFree(d_ws);
     if (d_coef16) hipFree(d_coef16);
-    if (d_dft16) hipFree(d_dft16);
+    if (d_w256) hipFree(d_w256);
   }
 };
 
@@ -282,13 +282,27 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
       for (int t = 0; t < taps; ++t) sc += std::fabs((double)half_to_float(h16[(size_t)t * N + c]));
       smax = sc > smax ? sc : smax;
     }
-    int e1 = smax > 0.0 ? (int)std::ceil(std::log2(128.0 * 256.0 * smax / 60000.0)) : 0;
-    e1 = e1 < -8 ? -8 : (e1 > 24 ? 24 : e1);
+    // Bounds on e1: >= -8 keeps 128 * 2^-e1 in FP16 range, <= 24 keeps every
+    // int8 sample times 2^-e1 exact; the output scale 2^(e1-s) is folded into
+    // the FP16 stage-3 DFT matrix, exact for e1 - s in [-12, 15]. Among the
+    // admissible values the smallest (the most FP16 headroom used) is taken.
+    const int e1_range = smax > 0.0 ? (int)std::ceil(std::log2(128.0 * 256.0 * smax / 60000.0)) : -8;
+    int e1 = e1_range;
+    if (e1 < -8) e1 = -8;
+    if (e1 < coeff_shift - 12) e1 = coeff_shift - 12;
+    const int e1_hi = coeff_shift + 15 < 24 ? coeff_shift + 15 : 24;
+    if (e1 > e1_hi) {
+      delete p;
+      fail(PPF_ERR_UNSUPPORTED,
+           "fft_mode=MFMA_F16: FP16 coefficients with sum_t |h16| up to %.6g need a sample scale beyond "
+           "2^-%d; raise coeff_shift or scale the coefficients down", smax, e1_hi);
+      return nullptr;
+    }
     p->mfma_e1 = e1;
     if ((e = hipMalloc(&p->d_coef16, lane.size() * 2)) != hipSuccess) { p->d_coef16 = nullptr; goto hip_fail; }
-    if ((e = hipMalloc(&p->d_dft16, 64)) != hipSuccess) { p->d_dft16 = nullptr; goto hip_fail; }
+    if ((e = hipMalloc(&p->d_w256, 256 * 4)) != hipSuccess) { p->d_w256 = nullptr; goto hip_fail; }
     if ((e = hipMemcpy(p->d_coef16, lane.data(), lane.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
-    if ((e = ppf::launch_dft16(p->d_dft16, nullptr)) != hipSuccess) goto hip_fail;
+    if ((e = ppf::launch_w256(p->d_w256, nullptr)) != hipSuccess) goto hip_fail;
   }
   if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) goto hip_fail;
   g_status = PPF_OK;

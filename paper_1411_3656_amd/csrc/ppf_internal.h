@@ -90,15 +90,15 @@ hipError_t launch_history(const void* old_hist, const void* chunk, void* new_his
 struct MfmaDev {
   const void* coef16;  // 16 tap slots x 4096 FP16 coefficients in lane order
   const void* tw;      // 4096 complex FP32 twiddles
-  const void* dft16;   // 16 complex FP16 values exp(-2 pi i k/16)
+  const void* w256;    // 256 complex FP16 values exp(-2 pi i k/256)
   int d;               // leading zero tap slots (16 - T)
   float in_scale;      // 2^-e1 applied to the int8 samples (exact in FP16)
-  float out_scale;     // 2^(e1 - coeff_shift) applied to the FP32 spectra
+  float out_scale;     // 2^(e1 - coeff_shift), folded exactly into the FP16 stage-3 matrix
 };
 bool mfma_available(int N, int TP);
 size_t mfma_coef_bytes();
 void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst);
-hipError_t launch_dft16(void* table, hipStream_t st);
+hipError_t launch_w256(void* table, hipStream_t st);
 hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st);
 
 }  // namespace ppf

@@ -7,10 +7,13 @@
 // What is computed (section 2, Eq. 1 per channel, then the DFT of section 3):
 //   u[m][c] = sum_t h[t][c] x[m+t][c],   X[m][k] = sum_c u[m][c] W^(c k),
 // W = exp(-2 pi i / 4096). With c = c0 + 256 p (c0 = a + 16 b) and
-// k = k1 + 16 k2 + 256 k3 the DFT factors as
-//   X = sum_a W16^(a k3) W256^(a k2) sum_b W16^(b k2) W^(c0 k1) sum_p W16^(p k1) u[c0 + 256 p],
-// i.e. stage 1 (16-point DFTs over p), twiddle W^(c0 k1), stage 2 (over b),
-// twiddle W256^(a k2), stage 3 (over a).
+// k = k1 + 16 k2 + 256 k3 the exponent c k splits (mod 4096) so that
+//   X = sum_a W16^(a k3) W^(a (k1 + 16 k2)) sum_b W256^(b (16 k2 + k1)) sum_p W16^(p k1) u[a + 16 b + 256 p]:
+// stage 1 is a plain 16-point DFT over p, stage 2 a 16-point transform over
+// b whose matrix W256^(b (16 k2 + k1)) also carries the usual inter-stage
+// twiddle W256^(b k1) (k1 is the same for all vectors of a wave there), one
+// FP32 twiddle W^(a (k1 + 16 k2)) follows stage 2, and stage 3 is a plain
+// 16-point DFT over a.
 //
 // One workgroup of 1024 threads (16 waves) owns a tile of consecutive
 // spectra. A 16-point complex DFT of 16 vectors is two MFMAs: the DFT
@@ -55,13 +58,10 @@ constexpr int kThreads = 1024;
 constexpr int kCoefBytes = kTaps * kN * 2;      // FP16 coefficients in LDS
 constexpr int kXchgBytes = kN * 4;              // one FP16 complex exchange buffer
 constexpr int kLdsBytes = kCoefBytes + 2 * kXchgBytes;
-#ifndef PPF_MFMA_TW_REGS
-#define PPF_MFMA_TW_REGS 1
-#endif
 #ifndef PPF_MFMA_COEF_GROUP
-#define PPF_MFMA_COEF_GROUP 2
+#define PPF_MFMA_COEF_GROUP 0
 #endif
-constexpr int kCoefGroup = PPF_MFMA_COEF_GROUP;   // taps per batch of coefficient reads
+constexpr int kCoefGroup = PPF_MFMA_COEF_GROUP;   // taps per batch of coefficient reads (0: free)
 
 constexpr int kBufDword3 = 0x00020000;
 constexpr int kAuxNt = 2;
@@ -101,14 +101,14 @@ struct MfmaParams {
   v2f* out;                  // complex FP32 spectra
   const uint4* coef;         // [16][4096] FP16 coefficients in lane order
   const v2f* tw;             // 4096 FP32 twiddles exp(-2 pi i k / 4096)
-  const uint32_t* dft16;     // 16 FP16 complex exp(-2 pi i k / 16), (re, im) packed
+  const uint32_t* w256;      // 256 FP16 complex exp(-2 pi i k / 256), (re, im) packed
   int h0;
   int M;                     // spectra
   int S;                     // spectra per tile
   int d;                     // leading zero tap slots (16 - T)
   int nblocks;
   float in_scale;            // 2^-e1
-  float out_scale;           // 2^(e1 - s)
+  float out_scale;           // 2^(e1 - s), exact on the FP16 stage-3 matrix
 };
 
 namespace {
@@ -130,12 +130,8 @@ struct MfmaEngine {
   uint32_t in_off;           // lane byte offset in an input block (channel 16w+j+1024h)
   uint32_t out_off;          // lane byte offset in an output spectrum
   uint32_t wr1, wr2, rd;     // swizzled exchange byte offsets (r = 0 terms)
-  h8 a_re;                   // DFT-16 matrix row of this lane (real parts of the outputs)
-#if PPF_MFMA_TW_REGS
-  v2f tw1[4], tw2[4];        // stage twiddles of this lane's outputs
-#else
-  int tw1i, tw1s, tw2i;      // twiddle indices of output r: tw1i + r*tw1s, tw2i + r*16j (mod N)
-#endif
+  h8 a1, a2, a3;             // A operands (real-part rows) of stages 1, 2, 3
+  v2f tw2[4];                // FP32 twiddles after stage 2 of this lane's outputs
   h2 sc, bias;
 
   __device__ __forceinline__ MfmaEngine(const MfmaParams& p_, uint8_t* lds_) : p(p_), lds(lds_) {}
@@ -187,46 +183,42 @@ struct MfmaEngine {
     for (int i = 0; i < kCoefBytes / 16 / kThreads; ++i)
       ((uint4*)lds)[tid + i * kThreads] = p.coef[tid + i * kThreads];
 
-    // A operand: row j of the DFT-16 matrix for real outputs, inputs
-    // (p, re/im) for p = 4h + e: (wr, -wi) with W16^(p j) = wr + i wi
+    // A operands, real-part row j, inputs (point 4h+e, re/im): (wr, -wi) of
+    // stage 1: W16^(p j); stage 2 (wave w holds k1 = w): W256^(b (16 j + w));
+    // stage 3: W16^(a j) times the output scale (a power of two, exact)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const h2 wv = __builtin_bit_cast(h2, p.dft16[((4 * h + e) * j) & 15]);
-      a_re[2 * e] = wv.x;
-      a_re[2 * e + 1] = -wv.y;
+      const int q = 4 * h + e;
+      const h2 w1 = __builtin_bit_cast(h2, p.w256[(16 * q * j) & 255]);
+      const h2 w2 = __builtin_bit_cast(h2, p.w256[(q * (16 * j + w)) & 255]);
+      a1[2 * e] = w1.x;
+      a1[2 * e + 1] = -w1.y;
+      a2[2 * e] = w2.x;
+      a2[2 * e + 1] = -w2.y;
+      a3[2 * e] = (_Float16)((float)w1.x * p.out_scale);
+      a3[2 * e + 1] = (_Float16)(-(float)w1.y * p.out_scale);
     }
-#if PPF_MFMA_TW_REGS
+    // stage-2 outputs of this lane: vector (a = j, k1 = w), k2 = 4h + r
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      tw1[r] = p.tw[((16 * w + j) * (4 * h + r)) & (kN - 1)];
-      tw2[r] = p.tw[(16 * j * (4 * h + r)) & (kN - 1)];
-    }
-#else
-    tw1i = ((16 * w + j) * 4 * h) & (kN - 1);
-    tw1s = 16 * w + j;
-    tw2i = (16 * j * 4 * h) & (kN - 1);
-#endif
-  }
-
-  // twiddles of this lane's 4 outputs: index i0 + r*step (mod N), read from
-  // the FP32 table (32 KiB, stays in the vector L1/L2)
-  __device__ __forceinline__ void twiddles(int i0, int step, v2f (&tw)[4]) const {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tw[r] = p.tw[(i0 + r * step) & (kN - 1)];
+    for (int r = 0; r < 4; ++r) tw2[r] = p.tw[(j * (w + 16 * (4 * h + r))) & (kN - 1)];
   }
 
   // Re X = A_re . (xr, xi) and Im X = A_re . (xi, -xr): the -i rotation of
   // the inputs replaces a second matrix (one packed multiply per register)
-  __device__ __forceinline__ void dft16(const h8& b, f4& dre, f4& dim) const {
+  __device__ __forceinline__ void dft16(const h8& a, const h8& b, f4& dre, f4& dim) const {
     const f4 z = {0.f, 0.f, 0.f, 0.f};
-    dre = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_re, b, z, 0, 0, 0);
-    h8 bi;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      bi[2 * e] = b[2 * e + 1];
-      bi[2 * e + 1] = -b[2 * e];
-    }
-    dim = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_re, bi, z, 0, 0, 0);
+    dre = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, z, 0, 0, 0);
+    // (re, im) -> (im, -re) per register: one packed multiply by (1, -1)
+    // with the halves of the first operand swapped by op_sel
+    const uint4 bu = __builtin_bit_cast(uint4, b);
+    uint4 bq;
+    const uint32_t one_neg = 0xBC003C00u;   // FP16 (1.0, -1.0)
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.x) : "v"(bu.x), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.y) : "v"(bu.y), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.z) : "v"(bu.z), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.w) : "v"(bu.w), "s"(one_neg));
+    const h8 bi = __builtin_bit_cast(h8, bq);
+    dim = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, bi, z, 0, 0, 0);
   }
 
   // twiddle in FP32, round to FP16, scatter to the next stage's layout
@@ -241,6 +233,14 @@ struct MfmaEngine {
       const float yi = fmaf(dre[r], tw[r].y, dim[r] * tw[r].x);
       dst[256 * r] = pack_h2(yr, yi);
     }
+  }
+
+  // stage-1 outputs need no twiddle: round to FP16 and scatter
+  __device__ __forceinline__ void plain_store(const f4& dre, const f4& dim, uint32_t base) const {
+    asm volatile("" : "+v"(base));
+    uint32_t* dst = (uint32_t*)(lds + base);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[256 * r] = pack_h2(dre[r], dim[r]);
   }
 
   __device__ __forceinline__ h8 read_vec(int buf) const {
@@ -272,11 +272,14 @@ struct MfmaEngine {
     for (int s = 0; s < PF; ++s) load(stage[s], m0 + kTaps - 1 + s);
     __syncthreads();   // coefficients in LDS
 
+    // Tiles hold a multiple of 16 spectra except the last; its extra steps
+    // run on zero input and their stores get an empty range (discarded), so
+    // the 16 unrolled steps have no branches and the scheduler can overlap
+    // one spectrum's last DFT stage with the next spectrum's FIR.
     for (int base = 0; base < ng; base += kTaps) {
 #pragma unroll
       for (int k = 0; k < kTaps; ++k) {
         const int it = base + k;
-        if (it < ng) {   // uniform over the block; keeps the loop fully unrolled
         // block it+15 into the slot of block it-1; refill its staging slot
         widen(stage[k % PF], ring[(k + kTaps - 1) % kTaps]);
         load(stage[k % PF], m0 + it + kTaps - 1 + PF);
@@ -292,7 +295,7 @@ struct MfmaEngine {
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) {
           // coefficient reads issued a few taps ahead, not all at once
-          if (t % kCoefGroup == 0) __builtin_amdgcn_sched_barrier(0);
+          if (kCoefGroup > 0 && t % kCoefGroup == 0) __builtin_amdgcn_sched_barrier(0);
           const h4 hv = *(const h4*)(lds + t * (kN * 2) + tid * 8);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -301,7 +304,7 @@ struct MfmaEngine {
             ai[e] = fmaf((float)hv[e], (float)xv.y, ai[e]);
           }
         }
-        __builtin_amdgcn_sched_barrier(0);
+        if (kCoefGroup > 0) __builtin_amdgcn_sched_barrier(0);
         h8 b;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -309,36 +312,23 @@ struct MfmaEngine {
           b[2 * e + 1] = (_Float16)ai[e];
         }
 
-#if PPF_MFMA_TW_REGS
         f4 dre, dim;
-        dft16(b, dre, dim);                       // stage 1 over p
-        twiddle_store(dre, dim, tw1, wr1);        // W^(c0 k1), to stage-2 layout (X)
+        dft16(a1, b, dre, dim);                   // stage 1 over p
+        plain_store(dre, dim, wr1);               // to the stage-2 layout (X)
         __syncthreads();
-        dft16(read_vec(X), dre, dim);             // stage 2 over b
-        twiddle_store(dre, dim, tw2, wr2);        // W256^(a k2), to stage-3 layout (Y)
-#else
-        v2f tw[4];
-        twiddles(tw1i, tw1s, tw);
-        f4 dre, dim;
-        dft16(b, dre, dim);                       // stage 1 over p
-        twiddle_store(dre, dim, tw, wr1);         // W^(c0 k1), to stage-2 layout (X)
-        twiddles(tw2i, 16 * j, tw);
+        dft16(a2, read_vec(X), dre, dim);         // stage 2 over b (with W256^(b k1))
+        twiddle_store(dre, dim, tw2, wr2);        // W^(a (k1 + 16 k2)), to the stage-3 layout (Y)
         __syncthreads();
-        dft16(read_vec(X), dre, dim);             // stage 2 over b
-        twiddle_store(dre, dim, tw, wr2);         // W256^(a k2), to stage-3 layout (Y)
-#endif
-        __syncthreads();
-        dft16(read_vec(Y), dre, dim);             // stage 3 over a
+        dft16(a3, read_vec(Y), dre, dim);         // stage 3 over a, output scale folded in
 
-        const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * kN, kN * 8);
+        const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * kN, it < ng ? kN * 8 : 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           v2f o;
-          o.x = dre[r] * p.out_scale;
-          o.y = dim[r] * p.out_scale;
+          o.x = dre[r];
+          o.y = dim[r];
           __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, o),
                                                 rs, out_off, (uint32_t)(2048 * r), kAuxNt);
-        }
         }
       }
     }
@@ -355,11 +345,11 @@ __global__ void __launch_bounds__(kThreads) ppf_mfma_kernel(MfmaParams p) {
   eng.run();
 }
 
-__global__ void ppf_dft16_kernel(uint32_t* t) {
-  const int k = threadIdx.x;
-  if (k < 16) {
+__global__ void ppf_w256_kernel(uint32_t* t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 256) {
     double s, c;
-    sincospi(-2.0 * (double)k / 16.0, &s, &c);   // exact angle, rounded once to FP16
+    sincospi(-2.0 * (double)k / 256.0, &s, &c);   // exact angle, rounded once to FP16
     h2 v;
     v.x = (_Float16)c;
     v.y = (_Float16)s;
@@ -405,8 +395,8 @@ void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst) {
       }
 }
 
-hipError_t launch_dft16(void* table, hipStream_t st) {
-  hipLaunchKernelGGL(ppf_dft16_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)table);
+hipError_t launch_w256(void* table, hipStream_t st) {
+  hipLaunchKernelGGL(ppf_w256_kernel, dim3(1), dim3(256), 0, st, (uint32_t*)table);
   return hipGetLastError();
 }
 
@@ -436,12 +426,14 @@ hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st) {
     p.out = (v2f*)a.out + (size_t)s0 * kN;
     p.coef = (const uint4*)md.coef16;
     p.tw = (const v2f*)md.tw;
-    p.dft16 = (const uint32_t*)md.dft16;
+    p.w256 = (const uint32_t*)md.w256;
     p.M = (int)k;
+    // tiles of a multiple of 16 spectra (the unrolled step count), about
+    // one per CU
     const int cus = cu_count();
-    int S = (int)((k + cus - 1) / cus);
-    if (S < 1) S = 1;
-    p.S = S;
+    long long S = (k + cus - 1) / cus;
+    S = (S + 15) / 16 * 16;
+    p.S = (int)S;
     p.nblocks = (int)((k + S - 1) / S);
     p.d = md.d;
     p.in_scale = md.in_scale;
