@@ -87,7 +87,7 @@ def cpu_baseline(cfg, h32, budget_s: float = 12.0):
     total_s, done = 0.0, 0
     x = signals.complex_gaussian((spectra + taps - 1) * n, 1.0, seed=cfg["seed"] + 77)
     oracle.ppf(x[: (16 + taps - 1) * n], h32, n, taps)            # warm the BLAS pools
-    while total_s < budget_s and done < 64:
+    while total_s < budget_s and done < 4096:
         t0 = time.perf_counter()
         oracle.ppf(x, h32, n, taps)
         total_s += time.perf_counter() - t0

@@ -75,7 +75,8 @@ hipError_t launch_fft_desc(const PlanDev& pd, const DescClass* cls, const TileDe
                            hipStream_t st);
 hipError_t launch_fir_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                            hipStream_t st);
-hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, hipStream_t st);
+hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, long long max_samples,
+                               hipStream_t st);
 // One-time set-up of a plan's descriptor launchers, to run before capture.
 hipError_t prepare_desc(const PlanDev& pd, bool fused);
 // FP64 twiddle generation: tw[k] = exp(-2 pi i k/N) rounded to FP32.

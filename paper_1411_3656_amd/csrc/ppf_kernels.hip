@@ -771,14 +771,20 @@ __global__ void ppf_history_kernel(const E* old_h, const E* chunk, E* new_h, lon
 
 // Descriptor form: entry e writes the last hs samples of (a ++ b) to dst,
 // a holding the hs samples before b and b holding cs samples.
+// Block (x, y) copies piece x (kHistPiece samples) of entries y, y + gridDim.y, ...
+constexpr int kHistPiece = 1024;
 __global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count, const HistDesc* h) {
   const int n = *count;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  for (int e = blockIdx.y; e < n; e += gridDim.y) {
     const HistDesc hd = h[e];
+    const int i0 = blockIdx.x * kHistPiece;
+    if (i0 >= hd.hs) continue;
     const v2f* a = (const v2f*)hd.a;
     const v2f* b = (const v2f*)hd.b;
     v2f* dst = (v2f*)hd.dst;
-    for (int i = threadIdx.x; i < hd.hs; i += 256) {
+    const int i1 = i0 + kHistPiece < hd.hs ? i0 + kHistPiece : hd.hs;
+#pragma unroll 4
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
       const long long k = (long long)i + hd.cs;
       dst[i] = k < hd.hs ? a[k] : b[k - hd.hs];
     }
@@ -1141,7 +1147,8 @@ hipError_t launch_fft_desc(const PlanDev& pd, const DescClass* cls, const TileDe
 template <int TP>
 static hipError_t fir_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                                   hipStream_t st) {
-  constexpr int PF = TP >= 32 ? 2 : 4;
+  // serving tiles are short and few: more loads in flight per thread
+  constexpr int PF = TP >= 32 ? 2 : 8;
   auto kern = &ppf_fir_desc_kernel<TP, PF>;
   static const int occ = [&] {
     KernelInfo ki{(const void*)kern, 256, 1, 0};
@@ -1184,9 +1191,15 @@ hipError_t prepare_desc(const PlanDev& pd, bool fused) {
   return e;
 }
 
-hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, hipStream_t st) {
-  int grid = max_entries < 1 ? 1 : (max_entries > 1024 ? 1024 : max_entries);
-  hipLaunchKernelGGL(ppf_history_desc_kernel, dim3(grid), dim3(256), 0, st, count, h);
+hipError_t launch_history_desc(const int* count, const HistDesc* h, int max_entries, long long max_samples,
+                               hipStream_t st) {
+  const long long px = (max_samples + kHistPiece - 1) / kHistPiece;
+  const int gx = (int)(px < 1 ? 1 : px);
+  // entries are strided over gridDim.y; about 4096 blocks in all
+  long long gy = 4096 / gx;
+  if (gy > max_entries) gy = max_entries;
+  if (gy < 1) gy = 1;
+  hipLaunchKernelGGL(ppf_history_desc_kernel, dim3(gx, (unsigned)gy), dim3(256), 0, st, count, h);
   return hipGetLastError();
 }
 

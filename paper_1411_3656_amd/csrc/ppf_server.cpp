@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -40,11 +41,25 @@
 
 namespace {
 
+#ifndef PPF_SERVER_FIR_TILE
+#define PPF_SERVER_FIR_TILE 32
+#endif
+// Batches of different slots on their own streams (concurrent on the GPU);
+// a stream then joins a batch only when none of its chunks is in flight.
+#ifndef PPF_SERVER_CONCURRENT_SLOTS
+#define PPF_SERVER_CONCURRENT_SLOTS 0
+#endif
+// Fused/FFT tile length per class chosen to spread each class over about
+// this many tiles (0: fixed tiles of about 32K samples).
+#ifndef PPF_SERVER_TARGET_TILES
+#define PPF_SERVER_TARGET_TILES 256
+#endif
 constexpr int kMaxClasses = 8;
-constexpr int kMaxTiles = 2048;       // per batch, all classes
+constexpr int kMaxTiles = 6144;       // per batch, all classes
+constexpr int kTargetTiles = PPF_SERVER_TARGET_TILES;   // tiles per plan class and batch
 constexpr int kMaxHist = 512;         // history entries per batch
 constexpr int kMaxSlots = 4;
-constexpr size_t kSlotWorkspace = 64ull << 20;   // two-pass presums per batch
+constexpr size_t kSlotWorkspace = 256ull << 20;  // two-pass presums per batch
 
 long long now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -59,8 +74,8 @@ struct DescArea {
   ppf::DescClass fft[kMaxClasses];
   int nhist;
   int pad_[3];
-  ppf::TileDesc tiles[kMaxTiles];
   ppf::HistDesc hist[kMaxHist];
+  ppf::TileDesc tiles[kMaxTiles];   // last: a batch uploads only the tiles it uses
 };
 
 struct PendingChunk {
@@ -80,6 +95,7 @@ struct SrvStream {
   bool closing = false;
   std::deque<PendingChunk> queue;   // scheduler-owned
   long long outstanding = 0;        // submitted, not completed
+  long long inflight = 0;           // in a launched batch, not completed (scheduler-owned)
 };
 
 struct DoneChunk {
@@ -93,6 +109,8 @@ struct DoneChunk {
 struct Slot {
   DescArea* host = nullptr;        // pinned
   DescArea* dev = nullptr;
+  size_t upload_bytes = 0;         // used prefix of the descriptor area
+  hipStream_t stream = nullptr;    // batches of different slots run concurrently
   void* ws = nullptr;
   hipEvent_t done = nullptr;
   hipEvent_t start = nullptr;      // timing: recorded before the graph
@@ -106,7 +124,9 @@ struct ClassInfo {
   ppf_plan_t plan = nullptr;
   int N = 0, T = 0;
   bool fused = true;
-  int tile_spectra = 16;
+  int tile_spectra = 16;       // fused and FFT-pass tiles (spread over workgroups)
+  int fir_tile_spectra = PPF_SERVER_FIR_TILE;   // FIR-pass tiles (channels give the parallelism; long tiles
+                               // read the T-1 halo blocks fewer times)
 };
 
 thread_local int s_status = PPF_OK;
@@ -138,6 +158,8 @@ struct ppf_server_s {
   hipStream_t branch[kMaxClasses] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kMaxClasses] = {};
+  hipStream_t hist_branch = nullptr;   // history updates of a batch
+  hipEvent_t hist_join = nullptr;
 
   std::mutex mu;                   // guards everything below
   std::condition_variable cv;      // wakes the scheduler, signals drains
@@ -196,9 +218,17 @@ int build_graph(ppf_server_s* s, Slot& sl) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(s->launch, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return sfail_hip(e, "graph capture begin");
-  e = hipMemcpyAsync(sl.dev, sl.host, sizeof(DescArea), hipMemcpyHostToDevice, s->launch);
-  if (e == hipSuccess) e = hipEventRecord(s->fork, s->launch);
+  // the descriptor upload precedes each launch (only the used bytes)
+  e = hipEventRecord(s->fork, s->launch);
   const int nc = (int)s->classes.size();
+  // history updates read only the old history and the chunks: a branch of
+  // their own, beside the transforms
+  long long max_hist = 1;
+  for (const ClassInfo& ci : s->classes) max_hist = std::max<long long>(max_hist, (long long)(ci.T - 1) * ci.N);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->hist_branch, s->fork, 0);
+  if (e == hipSuccess) e = ppf::launch_history_desc(&sl.dev->nhist, sl.dev->hist, kMaxHist, max_hist, s->hist_branch);
+  if (e == hipSuccess) e = hipEventRecord(s->hist_join, s->hist_branch);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->launch, s->hist_join, 0);
   for (int c = 0; c < nc && e == hipSuccess; ++c) {
     hipStream_t b = s->branch[c];
     e = hipStreamWaitEvent(b, s->fork, 0);
@@ -213,7 +243,6 @@ int build_graph(ppf_server_s* s, Slot& sl) {
     if (e == hipSuccess) e = hipEventRecord(s->join[c], b);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->launch, s->join[c], 0);
   }
-  if (e == hipSuccess) e = ppf::launch_history_desc(&sl.dev->nhist, sl.dev->hist, kMaxHist, s->launch);
   hipError_t e2 = hipStreamEndCapture(s->launch, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) hipGraphDestroy(g);
@@ -254,21 +283,33 @@ void admit_waiting(ppf_server_s* s) {
 }
 
 // Fill slot `sl` from the admitted streams' FIFOs (scheduler thread, mu held).
-// Returns the number of chunks placed.
+// Phase 1 picks the chunks: per stream a run of consecutive chunks (each
+// but the last at least T-1 spectra long, so the history of the next one is
+// the tail of the previous one), skipping streams with chunks still in
+// flight. Phase 2 cuts them into tiles whose length per plan class spreads
+// the class over about kTargetTiles work items. Returns the chunk count.
 int form_batch(ppf_server_s* s, Slot& sl) {
   DescArea& d = *sl.host;
   const int nc = (int)s->classes.size();
-  std::vector<std::vector<ppf::TileDesc>> tf(nc), tr(nc), tt(nc);   // fused, FIR, FFT tiles
-  int ntiles = 0, nhist = 0;
+  struct Pick {
+    int cls;
+    const void* hist_src;   // the h blocks before the chunk
+    ppf_chunk c;
+    size_t ws_off;          // two-pass classes: presum offset in the slot workspace
+  };
+  std::vector<Pick> picks;
+  std::vector<long long> cls_spectra(nc, 0);
+  int nhist = 0, worst_tiles = 0;
   size_t ws_used = 0;
   sl.chunks.clear();
   for (auto& kv : s->streams) {
     SrvStream& st = *kv.second;
     if (!st.admitted || st.queue.empty()) continue;
+    if (PPF_SERVER_CONCURRENT_SLOTS && st.inflight > 0) continue;
     const ClassInfo& ci = s->classes[st.cls];
     const int N = ci.N, h = ci.T - 1;
     if (h > 0 && nhist >= kMaxHist) break;
-    const void* hist_src = st.hist[st.cur];   // the h blocks before the next chunk
+    const void* hist_src = st.hist[st.cur];
     const void* last_a = nullptr;
     const void* last_b = nullptr;
     long long last_cs = 0;
@@ -276,44 +317,16 @@ int form_batch(ppf_server_s* s, Slot& sl) {
     while (!st.queue.empty()) {
       const PendingChunk& pc = st.queue.front();
       const long long S = pc.c.nspectra;
-      const int ts = ci.tile_spectra;
-      const int nt = (int)((S + ts - 1) / ts);
-      const int tiles_needed = ci.fused ? nt : 2 * nt;
+      // tile count at the longest tiles bounds what phase 2 can emit
+      const int nt = (int)((S + ci.tile_spectra - 1) / ci.tile_spectra);
+      const int ntr = (int)((S + ci.fir_tile_spectra - 1) / ci.fir_tile_spectra);
+      const int tiles_needed = ci.fused ? nt : nt + ntr;
       const size_t ws_needed = ci.fused ? 0 : (size_t)S * N * 8;
-      if (ntiles + tiles_needed > kMaxTiles || ws_used + ws_needed > kSlotWorkspace) break;
+      if (worst_tiles + tiles_needed > kMaxTiles || ws_used + ws_needed > kSlotWorkspace) break;
       if (taken > 0 && last_cs < (long long)h * N) break;   // history would not be contiguous
-      for (long long m = 0; m < S; m += ts) {
-        const int cnt = (int)std::min<long long>(ts, S - m);
-        ppf::TileDesc td;
-        // the tile reads blocks m .. m+cnt+h-1 of (the h history blocks ++ chunk)
-        if (m < h) {
-          td.x0 = (const char*)hist_src + (size_t)m * N * 8;
-          td.h0 = (int)(h - m);
-          td.x1 = pc.c.in;
-        } else {
-          td.x0 = pc.c.in;
-          td.h0 = 0;
-          td.x1 = (const char*)pc.c.in + (size_t)(m - h) * N * 8;
-        }
-        td.count = cnt;
-        void* out = (char*)pc.c.out + (size_t)m * N * 8;
-        if (ci.fused) {
-          td.out = out;
-          tf[st.cls].push_back(td);
-        } else {
-          void* u = (char*)sl.ws + ws_used + (size_t)m * N * 8;
-          td.out = u;
-          tr[st.cls].push_back(td);
-          ppf::TileDesc f2;
-          f2.x0 = u;
-          f2.x1 = u;
-          f2.h0 = 0;
-          f2.out = out;
-          f2.count = cnt;
-          tt[st.cls].push_back(f2);
-        }
-      }
-      ntiles += tiles_needed;
+      picks.push_back(Pick{st.cls, hist_src, pc.c, ws_used});
+      cls_spectra[st.cls] += S;
+      worst_tiles += tiles_needed;
       ws_used += ws_needed;
       last_a = hist_src;
       last_b = pc.c.in;
@@ -321,6 +334,7 @@ int form_batch(ppf_server_s* s, Slot& sl) {
       if (S >= h) hist_src = (const char*)pc.c.in + (size_t)(S - h) * N * 8;
       sl.chunks.push_back(DoneChunk{pc.c.tag, pc.arrival_ns, S * N * 8, S, st.id});
       st.queue.pop_front();
+      st.inflight++;
       taken++;
     }
     if (taken == 0) continue;
@@ -333,6 +347,72 @@ int form_batch(ppf_server_s* s, Slot& sl) {
       hd.cs = (int)last_cs;
       d.hist[nhist++] = hd;
       st.cur = 1 - st.cur;           // the batch writes the other buffer
+    }
+  }
+
+  // phase 2: tile lengths per class, then the tiles
+  std::vector<int> ts(nc), tsr(nc);
+  auto count_tiles = [&]() {
+    long long n = 0;
+    for (const Pick& pk : picks) {
+      const long long S = pk.c.nspectra;
+      n += (S + ts[pk.cls] - 1) / ts[pk.cls];
+      if (!s->classes[pk.cls].fused) n += (S + tsr[pk.cls] - 1) / tsr[pk.cls];
+    }
+    return n;
+  };
+  for (int c = 0; c < nc; ++c) {
+    const ClassInfo& ci = s->classes[c];
+    const long long want = kTargetTiles > 0 ? (cls_spectra[c] + kTargetTiles - 1) / kTargetTiles : ci.tile_spectra;
+    ts[c] = (int)std::max<long long>(1, std::min<long long>(ci.tile_spectra, want));
+    tsr[c] = ci.fir_tile_spectra;
+  }
+  if (count_tiles() > kMaxTiles)
+    for (int c = 0; c < nc; ++c) ts[c] = s->classes[c].tile_spectra;   // fits by phase 1
+  std::vector<std::vector<ppf::TileDesc>> tf(nc), tr(nc), tt(nc);   // fused, FIR, FFT tiles
+  for (const Pick& pk : picks) {
+    const ClassInfo& ci = s->classes[pk.cls];
+    const int N = ci.N, h = ci.T - 1;
+    const long long S = pk.c.nspectra;
+    // input tile of spectra m .. m+cnt-1: blocks m .. m+cnt+h-1 of (the h history blocks ++ chunk)
+    auto in_tile = [&](long long m, int cnt) {
+      ppf::TileDesc td;
+      if (m < h) {
+        td.x0 = (const char*)pk.hist_src + (size_t)m * N * 8;
+        td.h0 = (int)(h - m);
+        td.x1 = pk.c.in;
+      } else {
+        td.x0 = pk.c.in;
+        td.h0 = 0;
+        td.x1 = (const char*)pk.c.in + (size_t)(m - h) * N * 8;
+      }
+      td.count = cnt;
+      return td;
+    };
+    const int t1 = ts[pk.cls];
+    if (ci.fused) {
+      for (long long m = 0; m < S; m += t1) {
+        ppf::TileDesc td = in_tile(m, (int)std::min<long long>(t1, S - m));
+        td.out = (char*)pk.c.out + (size_t)m * N * 8;
+        tf[pk.cls].push_back(td);
+      }
+    } else {
+      char* u = (char*)sl.ws + pk.ws_off;
+      const int t2 = tsr[pk.cls];
+      for (long long m = 0; m < S; m += t2) {
+        ppf::TileDesc td = in_tile(m, (int)std::min<long long>(t2, S - m));
+        td.out = u + (size_t)m * N * 8;
+        tr[pk.cls].push_back(td);
+      }
+      for (long long m = 0; m < S; m += t1) {
+        ppf::TileDesc f2;
+        f2.x0 = u + (size_t)m * N * 8;
+        f2.x1 = f2.x0;
+        f2.h0 = 0;
+        f2.out = (char*)pk.c.out + (size_t)m * N * 8;
+        f2.count = (int)std::min<long long>(t1, S - m);
+        tt[pk.cls].push_back(f2);
+      }
     }
   }
   // lay the tiles out class by class
@@ -354,6 +434,7 @@ int form_batch(ppf_server_s* s, Slot& sl) {
     for (auto& t : tt[c]) d.tiles[at++] = t;
   }
   d.nhist = nhist;
+  sl.upload_bytes = offsetof(DescArea, tiles) + (size_t)at * sizeof(ppf::TileDesc);
   return (int)sl.chunks.size();
 }
 
@@ -372,7 +453,10 @@ void complete_slot(ppf_server_s* s, Slot& sl, long long t_done) {
     s->stat_bytes += dc.bytes;
     if (s->first_arrival < 0 || dc.arrival_ns < s->first_arrival) s->first_arrival = dc.arrival_ns;
     auto it = s->streams.find(dc.stream);
-    if (it != s->streams.end()) it->second->outstanding--;
+    if (it != s->streams.end()) {
+      it->second->outstanding--;
+      it->second->inflight--;
+    }
     s->outstanding--;
   }
   s->last_done = t_done;
@@ -443,10 +527,15 @@ void scheduler(ppf_server_s* s) {
     }
     if (progressed) s->cv.notify_all();
     if (s->stop && s->outstanding == 0 && idle) break;
-    // 3. launch into the next slot when it is free
-    Slot& sl = s->slots[s->next_slot];
+    // 3. launch into a free slot (the next in turn if it is free)
+    int free_k = -1;
+    for (int i = 0; i < s->nslots && free_k < 0; ++i) {
+      const int k = (s->next_slot + i) % s->nslots;
+      if (!s->slots[k].busy) free_k = k;
+    }
+    Slot& sl = s->slots[free_k < 0 ? s->next_slot : free_k];
     bool launched = false;
-    if (!sl.busy && s->async_error == PPF_OK) {
+    if (free_k >= 0 && s->async_error == PPF_OK) {
       bool any_ready = false;
       for (auto& kv : s->streams)
         if (kv.second->admitted && !kv.second->queue.empty()) { any_ready = true; break; }
@@ -460,16 +549,18 @@ void scheduler(ppf_server_s* s) {
         if (n > 0) {
           const long long tf1 = now_ns();
           lk.unlock();
-          hipError_t e = hipEventRecord(sl.start, s->launch);
-          if (e == hipSuccess) e = hipGraphLaunch(sl.exec, s->launch);
-          if (e == hipSuccess) e = hipEventRecord(sl.done, s->launch);
+          hipStream_t ls = PPF_SERVER_CONCURRENT_SLOTS ? sl.stream : s->launch;
+          hipError_t e = hipEventRecord(sl.start, ls);
+          if (e == hipSuccess) e = hipMemcpyAsync(sl.dev, sl.host, sl.upload_bytes, hipMemcpyHostToDevice, ls);
+          if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ls);
+          if (e == hipSuccess) e = hipEventRecord(sl.done, ls);
           const long long tf2 = now_ns();
           lk.lock();
           s->stat_form_us += (tf1 - tf0) * 1e-3;
           s->stat_launch_us += (tf2 - tf1) * 1e-3;
           sl.busy = true;
           s->stat_batches++;
-          s->next_slot = (s->next_slot + 1) % s->nslots;
+          s->next_slot = (free_k + 1) % s->nslots;
           if (e != hipSuccess) {
             s->async_error = PPF_ERR_HIP;
             complete_slot(s, sl, now_ns());
@@ -494,6 +585,10 @@ void destroy_server(ppf_server_s* s) {
   for (int k = 0; k < kMaxSlots; ++k) {
     Slot& sl = s->slots[k];
     if (sl.exec) hipGraphExecDestroy(sl.exec);
+    if (sl.stream) {
+      hipStreamSynchronize(sl.stream);
+      hipStreamDestroy(sl.stream);
+    }
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.start) hipEventDestroy(sl.start);
     if (sl.host) hipHostFree(sl.host);
@@ -508,6 +603,8 @@ void destroy_server(ppf_server_s* s) {
     if (s->branch[c]) hipStreamDestroy(s->branch[c]);
     if (s->join[c]) hipEventDestroy(s->join[c]);
   }
+  if (s->hist_branch) hipStreamDestroy(s->hist_branch);
+  if (s->hist_join) hipEventDestroy(s->hist_join);
   if (s->fork) hipEventDestroy(s->fork);
   if (s->launch) hipStreamDestroy(s->launch);
   delete s;
@@ -540,6 +637,8 @@ ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join[c], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->hist_branch, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->hist_join, hipEventDisableTiming);
   for (int k = 0; k < s->nslots && e == hipSuccess; ++k) {
     Slot& sl = s->slots[k];
     e = hipHostMalloc((void**)&sl.host, sizeof(DescArea), hipHostMallocDefault);
@@ -548,6 +647,7 @@ ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight) {
     if (e == hipSuccess) e = hipMalloc(&sl.ws, kSlotWorkspace);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
     if (e == hipSuccess) e = hipEventCreate(&sl.start);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
   }
   if (e != hipSuccess) {
     sfail_hip(e, "server creation");
@@ -722,6 +822,8 @@ int ppf_server_destroy(ppf_server_t s) {
   }
   if (s->worker.joinable()) s->worker.join();
   const int err = s->async_error;
+  for (int k = 0; k < s->nslots; ++k)
+    if (s->slots[k].stream) hipStreamSynchronize(s->slots[k].stream);
   hipStreamSynchronize(s->launch);
   destroy_server(s);
   return err == PPF_OK ? PPF_OK : sfail(err, "server had failed");
