@@ -32,28 +32,35 @@ struct PlanDev {
 };
 
 // Descriptor tables of the serving form (device memory, filled by the host).
-// A tile is a run of spectra whose input is x0 (h0 blocks) ++ x1 and whose
-// spectrum m goes to out + m*N.
+// A tile is a run of spectra whose input is x0 (h0 blocks) ++ x1 (h1
+// blocks) ++ x2 and whose spectrum m goes to out + m*N.
 struct TileDesc {
   const void* x0;
   const void* x1;
+  const void* x2;
   void* out;
   int h0;
+  int h1;
   int count;
+  int pad_;
 };
 // The tiles of one kernel class are tiles[first .. first+ntiles).
 struct DescClass {
   int first;
   int ntiles;
 };
-// History update: dst = last hs samples of (a ++ b); a holds the hs samples
-// before b, b holds cs samples (complex FP32).
+// History update: dst = last hs samples of (a0 ++ a1 ++ b); a0 holds n0 and
+// a1 hs - n0 samples (together the hs samples before b), b holds cs samples
+// (complex FP32).
 struct HistDesc {
-  const void* a;
+  const void* a0;
+  const void* a1;
   const void* b;
   void* dst;
+  int n0;
   int hs;
   int cs;
+  int pad_;
 };
 
 int taps_template(int T);                       // smallest supported TP >= T, 0 if none

@@ -408,19 +408,22 @@ struct FusedParams {
   int nblocks;
 };
 
-// One tile of spectra: the input is the concatenation x0 (h0 blocks) ++ x1,
-// spectrum m of the tile reads blocks m .. m+T-1 of it and is written to
-// out + m*N.
+// One tile of spectra: the input is the concatenation x0 (h0 blocks) ++ x1
+// (h01 - h0 blocks) ++ x2, spectrum m of the tile reads blocks m .. m+T-1
+// of it and is written to out + m*N.
 struct TileArgs {
   const v2f* x0;
   const v2f* x1;
+  const v2f* x2;
   v2f* out;
   int h0;
+  int h01;
 };
 
 template <int N>
 __device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
-  return rb < a.h0 ? a.x0 + (long long)rb * N : a.x1 + (long long)(rb - a.h0) * N;
+  return rb < a.h0 ? a.x0 + (long long)rb * N
+                   : (rb < a.h01 ? a.x1 + (long long)(rb - a.h0) * N : a.x2 + (long long)(rb - a.h01) * N);
 }
 
 // Per-block engine of the fused kernel: coefficients, twiddles and lane
@@ -562,7 +565,7 @@ ppf_fused_kernel(FusedParams p) {
 
   FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT> eng;
   eng.init(smem, grp, j, p.coef, p.tw, p.d);
-  TileArgs a{p.x0, p.x1, p.out, p.h0};
+  TileArgs a{p.x0, p.x1, p.x1, p.out, p.h0, p.h0};
   eng.run(a, m0, ng, niter);
 }
 
@@ -586,11 +589,11 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
   eng.init(smem, grp, j, coef, tw, d);
   for (int t0 = blockIdx.x * G; t0 < ntiles; t0 += gridDim.x * G) {
     const int t = t0 + grp;
-    TileArgs a{nullptr, nullptr, nullptr, 0};
+    TileArgs a{nullptr, nullptr, nullptr, nullptr, 0, 0};
     int count = 0;
     if (t < ntiles) {
       const TileDesc& td = tiles[first + t];
-      a = TileArgs{(const v2f*)td.x0, (const v2f*)td.x1, (v2f*)td.out, td.h0};
+      a = TileArgs{(const v2f*)td.x0, (const v2f*)td.x1, (const v2f*)td.x2, (v2f*)td.out, td.h0, td.h0 + td.h1};
       count = td.count;
     }
     int niter = count;
@@ -721,7 +724,10 @@ ppf_fir_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* co
     auto load = [&](v2f& dst, int vb) {
       if (vb >= vb_lo && vb < vb_hi) {
         const int rb = vb - d;
-        dst = rb < td.h0 ? ((const v2f*)td.x0)[(long long)rb * N + c] : ((const v2f*)td.x1)[(long long)(rb - td.h0) * N + c];
+        const int h01 = td.h0 + td.h1;
+        dst = rb < td.h0 ? ((const v2f*)td.x0)[(long long)rb * N + c]
+                         : (rb < h01 ? ((const v2f*)td.x1)[(long long)(rb - td.h0) * N + c]
+                                     : ((const v2f*)td.x2)[(long long)(rb - h01) * N + c]);
       }
     };
 #pragma unroll
@@ -769,8 +775,8 @@ __global__ void ppf_history_kernel(const E* old_h, const E* chunk, E* new_h, lon
   if (i < hs) new_h[i] = (i + cs < hs) ? old_h[i + cs] : chunk[i + cs - hs];
 }
 
-// Descriptor form: entry e writes the last hs samples of (a ++ b) to dst,
-// a holding the hs samples before b and b holding cs samples.
+// Descriptor form: entry e writes the last hs samples of (a0 ++ a1 ++ b) to
+// dst, a0 and a1 holding the hs samples before b and b holding cs samples.
 // Block (x, y) copies piece x (kHistPiece samples) of entries y, y + gridDim.y, ...
 constexpr int kHistPiece = 1024;
 __global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count, const HistDesc* h) {
@@ -779,14 +785,15 @@ __global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count,
     const HistDesc hd = h[e];
     const int i0 = blockIdx.x * kHistPiece;
     if (i0 >= hd.hs) continue;
-    const v2f* a = (const v2f*)hd.a;
+    const v2f* a0 = (const v2f*)hd.a0;
+    const v2f* a1 = (const v2f*)hd.a1;
     const v2f* b = (const v2f*)hd.b;
     v2f* dst = (v2f*)hd.dst;
     const int i1 = i0 + kHistPiece < hd.hs ? i0 + kHistPiece : hd.hs;
 #pragma unroll 4
     for (int i = i0 + threadIdx.x; i < i1; i += 256) {
       const long long k = (long long)i + hd.cs;
-      dst[i] = k < hd.hs ? a[k] : b[k - hd.hs];
+      dst[i] = k < hd.n0 ? a0[k] : (k < hd.hs ? a1[k - hd.n0] : b[k - hd.hs]);
     }
   }
 }

@@ -283,17 +283,43 @@ void admit_waiting(ppf_server_s* s) {
 }
 
 // Fill slot `sl` from the admitted streams' FIFOs (scheduler thread, mu held).
-// Phase 1 picks the chunks: per stream a run of consecutive chunks (each
-// but the last at least T-1 spectra long, so the history of the next one is
-// the tail of the previous one), skipping streams with chunks still in
-// flight. Phase 2 cuts them into tiles whose length per plan class spreads
-// the class over about kTargetTiles work items. Returns the chunk count.
+// Phase 1 picks the chunks: per stream a run of consecutive chunks. The T-1
+// blocks before a chunk (its "pre") are kept as at most two memory segments
+// (the tail of an older buffer and a short earlier chunk); a run stops where
+// the pre of the next chunk would need three. Streams with chunks still in
+// flight are skipped when batches run concurrently. Phase 2 cuts the chunks
+// into tiles whose length per plan class spreads the class over about
+// kTargetTiles work items. Returns the chunk count.
+struct Seg {
+  const char* p;
+  long long n;   // blocks
+};
+struct Pre {
+  Seg s[2];
+  int k = 0;     // segments in use
+};
+
+// the last `len` blocks of pre (len <= total), as segments
+static Pre pre_tail(const Pre& pre, long long len, int N) {
+  Pre out;
+  long long need = len;
+  Seg tmp[2];
+  int nt = 0;
+  for (int i = pre.k - 1; i >= 0 && need > 0; --i) {
+    const long long take = std::min(need, pre.s[i].n);
+    tmp[nt++] = Seg{pre.s[i].p + (size_t)(pre.s[i].n - take) * N * 8, take};
+    need -= take;
+  }
+  for (int i = nt - 1; i >= 0; --i) out.s[out.k++] = tmp[i];
+  return out;
+}
+
 int form_batch(ppf_server_s* s, Slot& sl) {
   DescArea& d = *sl.host;
   const int nc = (int)s->classes.size();
   struct Pick {
     int cls;
-    const void* hist_src;   // the h blocks before the chunk
+    Pre pre;                // the h blocks before the chunk
     ppf_chunk c;
     size_t ws_off;          // two-pass classes: presum offset in the slot workspace
   };
@@ -309,8 +335,9 @@ int form_batch(ppf_server_s* s, Slot& sl) {
     const ClassInfo& ci = s->classes[st.cls];
     const int N = ci.N, h = ci.T - 1;
     if (h > 0 && nhist >= kMaxHist) break;
-    const void* hist_src = st.hist[st.cur];
-    const void* last_a = nullptr;
+    Pre pre;
+    if (h > 0) pre.s[pre.k++] = Seg{(const char*)st.hist[st.cur], h};
+    Pre last_pre;
     const void* last_b = nullptr;
     long long last_cs = 0;
     int taken = 0;
@@ -323,15 +350,26 @@ int form_batch(ppf_server_s* s, Slot& sl) {
       const int tiles_needed = ci.fused ? nt : nt + ntr;
       const size_t ws_needed = ci.fused ? 0 : (size_t)S * N * 8;
       if (worst_tiles + tiles_needed > kMaxTiles || ws_used + ws_needed > kSlotWorkspace) break;
-      if (taken > 0 && last_cs < (long long)h * N) break;   // history would not be contiguous
-      picks.push_back(Pick{st.cls, hist_src, pc.c, ws_used});
+      if (pre.k > 2) break;   // this chunk's pre would need three segments
+      picks.push_back(Pick{st.cls, pre, pc.c, ws_used});
       cls_spectra[st.cls] += S;
       worst_tiles += tiles_needed;
       ws_used += ws_needed;
-      last_a = hist_src;
+      last_pre = pre;
       last_b = pc.c.in;
       last_cs = S * N;
-      if (S >= h) hist_src = (const char*)pc.c.in + (size_t)(S - h) * N * 8;
+      // the pre of the next chunk: the last h blocks of (pre ++ chunk)
+      if (h > 0) {
+        if (S >= h) {
+          pre = Pre();
+          pre.s[pre.k++] = Seg{(const char*)pc.c.in + (size_t)(S - h) * N * 8, h};
+        } else {
+          Pre next = pre_tail(pre, h - S, N);
+          if (next.k < 2) next.s[next.k] = Seg{(const char*)pc.c.in, S};
+          next.k++;   // three segments mark a run end (checked before the next chunk)
+          pre = next;
+        }
+      }
       sl.chunks.push_back(DoneChunk{pc.c.tag, pc.arrival_ns, S * N * 8, S, st.id});
       st.queue.pop_front();
       st.inflight++;
@@ -339,8 +377,11 @@ int form_batch(ppf_server_s* s, Slot& sl) {
     }
     if (taken == 0) continue;
     if (h > 0) {
+      // new history = last h blocks of (last_pre ++ last chunk)
       ppf::HistDesc hd;
-      hd.a = last_a;
+      hd.a0 = last_pre.s[0].p;
+      hd.n0 = (int)(last_pre.s[0].n * N);
+      hd.a1 = last_pre.k > 1 ? (const void*)last_pre.s[1].p : (const void*)last_pre.s[0].p;
       hd.b = last_b;
       hd.dst = st.hist[1 - st.cur];
       hd.hs = (int)(h * N);
@@ -374,18 +415,27 @@ int form_batch(ppf_server_s* s, Slot& sl) {
     const ClassInfo& ci = s->classes[pk.cls];
     const int N = ci.N, h = ci.T - 1;
     const long long S = pk.c.nspectra;
-    // input tile of spectra m .. m+cnt-1: blocks m .. m+cnt+h-1 of (the h history blocks ++ chunk)
+    // input tile of spectra m .. m+cnt-1: blocks m .. m+cnt+h-1 of (pre ++ chunk),
+    // at most three segments
     auto in_tile = [&](long long m, int cnt) {
-      ppf::TileDesc td;
-      if (m < h) {
-        td.x0 = (const char*)pk.hist_src + (size_t)m * N * 8;
-        td.h0 = (int)(h - m);
-        td.x1 = pk.c.in;
-      } else {
-        td.x0 = pk.c.in;
-        td.h0 = 0;
-        td.x1 = (const char*)pk.c.in + (size_t)(m - h) * N * 8;
+      Seg seg[3];
+      int k = 0;
+      long long skip = m;
+      for (int i = 0; i < pk.pre.k; ++i) {
+        if (skip >= pk.pre.s[i].n) {
+          skip -= pk.pre.s[i].n;
+          continue;
+        }
+        seg[k++] = Seg{pk.pre.s[i].p + (size_t)skip * N * 8, pk.pre.s[i].n - skip};
+        skip = 0;
       }
+      seg[k++] = Seg{(const char*)pk.c.in + (size_t)skip * N * 8, S + h};   // rest: the chunk
+      ppf::TileDesc td;
+      td.x0 = seg[0].p;
+      td.h0 = k > 1 ? (int)seg[0].n : 0;
+      td.x1 = k > 1 ? seg[1].p : seg[0].p;
+      td.h1 = k > 2 ? (int)seg[1].n : 0;
+      td.x2 = seg[k - 1].p;
       td.count = cnt;
       return td;
     };
@@ -408,7 +458,9 @@ int form_batch(ppf_server_s* s, Slot& sl) {
         ppf::TileDesc f2;
         f2.x0 = u + (size_t)m * N * 8;
         f2.x1 = f2.x0;
+        f2.x2 = f2.x0;
         f2.h0 = 0;
+        f2.h1 = 0;
         f2.out = (char*)pk.c.out + (size_t)m * N * 8;
         f2.count = (int)std::min<long long>(t1, S - m);
         tt[pk.cls].push_back(f2);

@@ -189,3 +189,47 @@ def test_submit_errors():
         ppf.ppf_server_create(1 << 20, 2)
     assert ei.value.status == ppf.PPF_ERR_BUDGET
     plan.close()
+
+
+def test_runs_of_short_chunks_match_oracle():
+    """Chunks shorter than T-1 spectra make a chunk's history span the old
+    history and earlier short chunks; several such streams, their chunks
+    submitted back to back, must still give the oracle's stream PPF."""
+    torch = _torch()
+    rng = np.random.default_rng(23)
+    plans = {}
+    streams = []
+    for i, (n, taps) in enumerate([(256, 16), (1024, 16), (4096, 16), (256, 8)]):
+        h = rng.standard_normal(taps * n).astype(np.float32)
+        plans[(n, taps)] = (ppf.Plan(n, taps, h), h)
+        lens = [2, 3, 1, 5, 2, 20, 1, 1, 1, 9, 4, 17, 1, 2] if n < 4096 else [2, 3, 1, 5, 2, 6, 1, 1]
+        x = signals.complex_gaussian(sum(lens) * n, 1.0, seed=900 + i)
+        chunks, at = [], 0
+        for s in lens:
+            chunks.append(x[at * n:(at + s) * n])
+            at += s
+        streams.append((n, taps, lens, chunks))
+    srv = ppf.ppf_server_create(1 << 32, 2)
+    try:
+        ids, outs, keep = [], [], []
+        for n, taps, lens, chunks in streams:
+            ids.append(ppf.ppf_server_open_stream(srv, plans[(n, taps)][0].handle))
+            outs.append([torch.full((s, n), float("nan"), dtype=torch.complex64, device="cuda") for s in lens])
+            keep.append([torch.from_numpy(c).cuda() for c in chunks])
+        torch.cuda.synchronize()
+        for i in range(max(len(s[2]) for s in streams)):
+            for k, (n, taps, lens, chunks) in enumerate(streams):
+                if i < len(lens):
+                    ppf.ppf_server_submit(srv, ids[k], keep[k][i], outs[k][i], lens[i], tag=k * 100 + i)
+        ppf.ppf_server_drain(srv, 120.0)
+        for k, (n, taps, lens, chunks) in enumerate(streams):
+            got = np.concatenate([o.cpu().numpy() for o in outs[k]])
+            ref = np.concatenate(oracle.ppf_stream(chunks, plans[(n, taps)][1], n, taps))
+            err = rel_err(got, ref)
+            print(f"short-chunk stream N={n} T={taps} err={err:.2e}")
+            assert err <= TOL, (n, taps, err)
+            ppf.ppf_server_close_stream(srv, ids[k])
+    finally:
+        ppf.ppf_server_destroy(srv)
+    for p, _ in plans.values():
+        p.close()
