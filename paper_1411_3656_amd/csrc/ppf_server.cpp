@@ -59,7 +59,7 @@ constexpr int kMaxTiles = 6144;       // per batch, all classes
 constexpr int kTargetTiles = PPF_SERVER_TARGET_TILES;   // tiles per plan class and batch
 constexpr int kMaxHist = 512;         // history entries per batch
 constexpr int kMaxSlots = 4;
-constexpr size_t kSlotWorkspace = 256ull << 20;  // two-pass presums per batch
+constexpr size_t kSlotWorkspace = 512ull << 20;  // two-pass presums per batch
 
 long long now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
