@@ -45,6 +45,12 @@ WORKLOADS = {
     "c2": dict(name="ska_lfaa_n1024_t8_2p27", N=1024, T=8, window="hamming", samples=1 << 27, tones=False,
                seed=signals.SEED_BASE + 1),
 }
+# The paper's Table 2 (its hardware; context, never the target): streaming
+# (data in device memory) and single mode (PCIe included) real-time multiples.
+PAPER_MC = {"2x Xeon E5-2650": 1.92, "Xeon Phi 5110P": 2.25, "GTX 580": 5.65, "Tesla K40": 6.89,
+            "GTX 750 Ti": 2.39}
+PAPER_MB = {"2x Xeon E5-2650": 1.92, "Xeon Phi 5110P": 0.40, "GTX 580": 0.37, "Tesla K40": 1.38,
+            "GTX 750 Ti": 0.82}
 SWEEP_N = [64, 512, 4096, 16384]
 SWEEP_T = [4, 8, 16, 32]
 
@@ -183,6 +189,7 @@ def line(workload, n, taps, m_total, ms, used_path, steps, warmup, traffic=None,
     }
     if cpu is not None:
         rec["cpu_baseline"] = cpu
+    rec["paper_context_mc"] = PAPER_MC
     return rec
 
 
@@ -191,7 +198,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep", "mb"])
     ap.add_argument("--load", type=float, default=50.0, help="serving: offered load in multiples of 6.5 GB/s")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
@@ -259,6 +267,78 @@ def main() -> int:
                                         "samples_per_s": round(n * m_total / (ms32 * 1e-3), 1),
                                         "path": {1: "fused", 2: "two_pass"}.get(used32)}
         print(json.dumps(rec), flush=True)
+        return 0
+
+    if args.workload == "mb":
+        # single mode (M_b of section 3): C2's input and output in page-locked
+        # host memory, moved over PCIe by the chunked pipeline
+        cfg = WORKLOADS["c2"]
+        n, taps = cfg["N"], cfg["T"]
+        m_total = cfg["samples"] // n - taps + 1
+        h32 = signals.design_coeffs(n, taps, cfg["window"]).astype(np.float32)
+        x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=cfg["seed"])
+        xin = torch.from_numpy(x).pin_memory()
+        del x
+        out = torch.empty((m_total, n), dtype=torch.complex64).pin_memory()
+        plan = ppf.Plan(n, taps, h32)
+        stream = torch.cuda.current_stream()
+        steps = min(args.steps, 20)
+        warm = min(args.warmup, 2)
+        for _ in range(warm):
+            plan.execute_host(xin, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            plan.execute_host(xin, out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        ms = ev0.elapsed_time(ev1) / steps
+        plan.close()
+        in_b = metrics.input_bytes(n, m_total)
+        gbps = in_b / (ms * 1e-3) / 1e9
+        pcie = (in_b + m_total * n * 8) / (ms * 1e-3) / 1e9
+        # the link's own rates with the same page-locked buffers: each
+        # direction alone, and both at once on two streams
+        dev_in = torch.empty(xin.shape, dtype=xin.dtype, device="cuda")
+        dev_out = torch.empty(out.shape, dtype=out.dtype, device="cuda")
+        s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+
+        def timed(fn, reps=3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps
+
+        def h2d():
+            with torch.cuda.stream(s_in):
+                dev_in.copy_(xin, non_blocking=True)
+
+        def d2h():
+            with torch.cuda.stream(s_out):
+                out.copy_(dev_out, non_blocking=True)
+
+        t_h2d = timed(h2d)
+        t_d2h = timed(d2h)
+        t_both = timed(lambda: (h2d(), d2h()))
+        link = {"h2d_gbps": round(in_b / t_h2d / 1e9, 2), "d2h_gbps": round(out.numel() * 8 / t_d2h / 1e9, 2),
+                "both_directions_gbps": round((in_b + out.numel() * 8) / t_both / 1e9, 2)}
+        del dev_in, dev_out
+        print(json.dumps({
+            "metric": METRIC, "value": round(gbps, 3), "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+            "ms_per_step": round(ms, 4), "host_wall_ms_per_step": round(wall * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "realtime_multiple_mb": round(metrics.realtime_multiple(gbps * 1e9), 2),
+            "pcie_gbps_in_plus_out": round(pcie, 2),
+            "pcie_copy_only": link,
+            "pcie_frac_of_copy_only": round(pcie / link["both_directions_gbps"], 3),
+            "config": {"workload": "single_mode_host_resident_n1024_t8_2p27", "N": n, "taps": taps,
+                       "nspectra": m_total, "host_memory": "page-locked", "chunk_input_bytes": 32 << 20},
+            "paper_context_mb": PAPER_MB}), flush=True)
         return 0
 
     if args.workload == "copy":

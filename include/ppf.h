@@ -151,6 +151,31 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value);
  */
 int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
 
+/*
+ * ppf_execute_host - the batch PPF on host-resident data (the single mode
+ * of section 3, whose throughput includes the PCIe transfers: the M_b
+ * measure of Table 2), enqueued asynchronously on the plan's stream.
+ *
+ * host_in:  host pointer, (nspectra + T - 1) * N samples of the plan's
+ *           input type.
+ * host_out: host pointer, nspectra * N complex FP32 spectra.
+ * chunk_spectra: spectra per pipeline chunk (0 selects about 32 MiB of
+ *           input per chunk).
+ *
+ * The batch is cut into chunks of consecutive spectra; chunk i's input
+ * (its spectra plus the T-1 blocks that follow) is copied to a device
+ * staging buffer on a copy stream while chunk i-1 is transformed on the
+ * plan's stream and chunk i-2's spectra are copied back on another copy
+ * stream. The plan's stream completes when every spectrum is in host_out.
+ * Host buffers must stay valid until then and should be page-locked
+ * (hipHostMalloc) for the copies to run asynchronously at full rate.
+ * The plan owns two pairs of staging buffers, allocated on first use.
+ * Errors as ppf_execute, plus PPF_ERR_NOMEM for the staging buffers.
+ * Not thread-safe against other calls on the same plan.
+ */
+int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long long nspectra,
+                     long long chunk_spectra);
+
 /* ppf_destroy - wait for the plan's stream, then free the plan. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);
 

@@ -97,6 +97,13 @@ struct ppf_plan_s {
   int mfma_e1 = 0;             // matrix-core mode: samples are scaled by 2^-e1
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  // single mode (host-resident data): staging buffers, copy streams, events
+  void* h_in[2] = {nullptr, nullptr};
+  void* h_out[2] = {nullptr, nullptr};
+  size_t h_in_cap = 0, h_out_cap = 0;
+  hipStream_t h2d = nullptr, d2h = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
+  hipEvent_t ev_start = nullptr;
   long long chunk_spectra = 0;
   hipStream_t stream = nullptr;
 
@@ -126,6 +133,16 @@ struct ppf_plan_s {
     if (d_ones) hipFree(d_ones);
     if (d_tw) hipFree(d_tw);
     if (d_ws) hipFree(d_ws);
+    for (int i = 0; i < 2; ++i) {
+      if (h_in[i]) hipFree(h_in[i]);
+      if (h_out[i]) hipFree(h_out[i]);
+      if (ev_in[i]) hipEventDestroy(ev_in[i]);
+      if (ev_comp[i]) hipEventDestroy(ev_comp[i]);
+      if (ev_out[i]) hipEventDestroy(ev_out[i]);
+    }
+    if (ev_start) hipEventDestroy(ev_start);
+    if (h2d) hipStreamDestroy(h2d);
+    if (d2h) hipStreamDestroy(d2h);
     if (d_coef16) hipFree(d_coef16);
     if (d_w256) hipFree(d_w256);
   }
@@ -197,6 +214,53 @@ int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* 
     if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
     e = ppf::launch_fft(pd, p->d_ws, (char*)out + (size_t)c0 * pd.N * 8, k, p->stream);
     if (e != hipSuccess) return fail_hip(e, "FFT kernel launch");
+  }
+  return PPF_OK;
+}
+
+// Single mode: staging buffers for chunks of `chunk` spectra (grown on demand).
+int ensure_host_pipe(ppf_plan_t p, long long chunk) {
+  const size_t sb = (size_t)sample_bytes(p->in_type);
+  const size_t in_need = (size_t)(chunk + p->T - 1) * p->N * sb;
+  const size_t out_need = (size_t)chunk * p->N * 8;
+  hipError_t e = hipSuccess;
+  if (!p->h2d) {
+    e = hipStreamCreateWithFlags(&p->h2d, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->d2h, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventCreateWithFlags(&p->ev_in[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_comp[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_out[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming);
+    if (e != hipSuccess) return fail_hip(e, "single-mode streams");
+  }
+  if (p->h_in_cap < in_need || p->h_out_cap < out_need) {
+    // earlier work on the staging buffers must be finished before they go
+    for (hipStream_t st : {p->stream, p->h2d, p->d2h}) {
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return fail_hip(e, "single-mode synchronize");
+    }
+    for (int i = 0; i < 2; ++i) {
+      if (p->h_in[i]) hipFree(p->h_in[i]);
+      if (p->h_out[i]) hipFree(p->h_out[i]);
+      p->h_in[i] = p->h_out[i] = nullptr;
+    }
+    p->h_in_cap = p->h_out_cap = 0;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipMalloc(&p->h_in[i], in_need);
+      if (e == hipSuccess) e = hipMalloc(&p->h_out[i], out_need);
+    }
+    if (e != hipSuccess) {
+      for (int i = 0; i < 2; ++i) {
+        if (p->h_in[i]) hipFree(p->h_in[i]);
+        if (p->h_out[i]) hipFree(p->h_out[i]);
+        p->h_in[i] = p->h_out[i] = nullptr;
+      }
+      return fail_hip(e, "single-mode staging buffers");
+    }
+    p->h_in_cap = in_need;
+    p->h_out_cap = out_need;
   }
   return PPF_OK;
 }
@@ -409,8 +473,67 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra) 
   }
 }
 
+int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long long nspectra,
+                     long long chunk_spectra) {
+  try {
+    if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+    if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
+    if (chunk_spectra < 0) return fail(PPF_ERR_INVALID, "chunk_spectra=%lld is negative", chunk_spectra);
+    if (nspectra == 0) { g_status = PPF_OK; return PPF_OK; }
+    if (!host_in || !host_out) return fail(PPF_ERR_INVALID, "host_in or host_out is NULL");
+    const size_t sb = (size_t)sample_bytes(plan->in_type);
+    const long long N = plan->N;
+    const size_t in_bytes = (size_t)(nspectra + plan->T - 1) * N * sb;
+    const size_t out_bytes = (size_t)nspectra * N * 8;
+    if (overlaps((uintptr_t)host_in, in_bytes, (uintptr_t)host_out, out_bytes))
+      return fail(PPF_ERR_INVALID, "host_in and host_out overlap");
+    long long chunk = chunk_spectra > 0 ? chunk_spectra : (long long)((32ull << 20) / ((size_t)N * sb));
+    if (chunk < 1) chunk = 1;
+    if (chunk > nspectra) chunk = nspectra;
+    int st = ensure_host_pipe(plan, chunk);
+    if (st != PPF_OK) return st;
+    // the copy streams start after what the plan's stream already holds
+    hipError_t e = hipEventRecord(plan->ev_start, plan->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->h2d, plan->ev_start, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->d2h, plan->ev_start, 0);
+    const long long nch = (nspectra + chunk - 1) / chunk;
+    for (long long i = 0; i < nch && e == hipSuccess; ++i) {
+      const int b = (int)(i & 1);
+      const long long m0 = i * chunk;
+      const long long k = nspectra - m0 < chunk ? nspectra - m0 : chunk;
+      const size_t kin = (size_t)(k + plan->T - 1) * N * sb;
+      // buffer b is free once chunk i-2 was transformed (input) and copied back (output)
+      if (i >= 2) e = hipStreamWaitEvent(plan->h2d, plan->ev_comp[b], 0);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->h_in[b], (const char*)host_in + (size_t)m0 * N * sb, kin, hipMemcpyHostToDevice,
+                           plan->h2d);
+      if (e == hipSuccess) e = hipEventRecord(plan->ev_in[b], plan->h2d);
+      if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in[b], 0);
+      if (e == hipSuccess && i >= 2) e = hipStreamWaitEvent(plan->stream, plan->ev_out[b], 0);
+      if (e != hipSuccess) break;
+      st = run_batch(plan, plan->h_in[b], 0, plan->h_in[b], plan->h_out[b], k);
+      if (st != PPF_OK) return st;
+      e = hipEventRecord(plan->ev_comp[b], plan->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(plan->d2h, plan->ev_comp[b], 0);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)host_out + (size_t)m0 * N * 8, plan->h_out[b], (size_t)k * N * 8,
+                           hipMemcpyDeviceToHost, plan->d2h);
+      if (e == hipSuccess) e = hipEventRecord(plan->ev_out[b], plan->d2h);
+    }
+    // the plan's stream completes after the last copy back
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_out[(nch - 1) & 1], 0);
+    if (e != hipSuccess) return fail_hip(e, "single-mode pipeline");
+    g_status = PPF_OK;
+    return PPF_OK;
+  } catch (...) {
+    return fail(PPF_ERR_NOMEM, "unexpected exception in ppf_execute_host");
+  }
+}
+
 int ppf_destroy(ppf_plan_t plan) {
   if (!plan) return PPF_OK;
+  if (plan->h2d) hipStreamSynchronize(plan->h2d);
+  if (plan->d2h) hipStreamSynchronize(plan->d2h);
   hipError_t e = hipStreamSynchronize(plan->stream);
   delete plan;
   if (e != hipSuccess) return fail_hip(e, "ppf_destroy synchronize");

@@ -68,6 +68,7 @@ _SIGNATURES = [
     ("ppf_plan_set_path", _c_int, [_c_vp, _c_int]),
     ("ppf_plan_query", _c_int, [_c_vp, _c_int, ctypes.POINTER(_c_ll)]),
     ("ppf_execute", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
+    ("ppf_execute_host", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_ll]),
     ("ppf_destroy", _c_int, [_c_vp]),
     ("ppf_stream_create", _c_vp, [_c_vp]),
     ("ppf_stream_push", _c_int, [_c_vp, _c_vp]),
@@ -138,12 +139,15 @@ def _handle(h):
 
 
 def _addr(buf) -> int | None:
-    """Address of a device buffer: an int, or an object with data_ptr()."""
+    """Address of a buffer: an int, an object with data_ptr() (a tensor), or
+    a numpy array."""
     if buf is None:
         return None
     if isinstance(buf, int):
         return buf
-    return int(buf.data_ptr())
+    if hasattr(buf, "data_ptr"):
+        return int(buf.data_ptr())
+    return int(buf.ctypes.data)
 
 
 # ---------------------------------------------------------------------------
@@ -184,6 +188,10 @@ def ppf_plan_query(plan: int, key: int) -> int:
 
 def ppf_execute(plan: int, inp, out, nspectra: int) -> int:
     return _check(lib().ppf_execute(plan, _addr(inp), _addr(out), int(nspectra)))
+
+
+def ppf_execute_host(plan: int, host_in, host_out, nspectra: int, chunk_spectra: int = 0) -> int:
+    return _check(lib().ppf_execute_host(plan, _addr(host_in), _addr(host_out), int(nspectra), int(chunk_spectra)))
 
 
 def ppf_destroy(plan: int) -> int:
@@ -320,6 +328,19 @@ class Plan:
         st = torch.cuda.current_stream(x.device) if stream is None else stream
         ppf_set_stream(self.handle, st.cuda_stream)
         ppf_execute(self.handle, x, out, nspectra)
+        return out
+
+    def execute_host(self, x, out, nspectra: int | None = None, chunk_spectra: int = 0, stream=None):
+        """Single mode: x and out are host tensors (page-locked for full
+        speed); the call is asynchronous on the plan's stream, which
+        completes once every spectrum is in out."""
+        import torch
+        if nspectra is None:
+            samples = x.numel() if x.is_complex() else x.shape[0]
+            nspectra = samples // self.N - self.T + 1
+        st = torch.cuda.current_stream() if stream is None else stream
+        ppf_set_stream(self.handle, st.cuda_stream)
+        ppf_execute_host(self.handle, x, out, nspectra, chunk_spectra)
         return out
 
     def close(self):
