@@ -4,4 +4,4 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg import
 this package; the product path never does.
 """
 from .ppf_oracle import (as_complex128, dft, dft_matrix_columns, fir_presum,  # noqa: F401
-                         n_spectra, ppf, ppf_stream, twiddles)
+                         n_spectra, ppf, ppf_power, ppf_stream, twiddles)

@@ -163,3 +163,21 @@ def ppf_stream(chunks, h, n_channels: int, taps: int) -> list[np.ndarray]:
         out.append(spectra[at:at + s])
         at += s
     return out
+
+
+def ppf_power(x, h, n_channels: int, taps: int, k_int: int) -> np.ndarray:
+    """Detected and integrated spectra: the power |X|^2 of each bin summed
+    over groups of k_int consecutive spectra (the screening step that follows
+    the filter bank in the pipeline of section 1).
+
+        P[j][k] = sum_{i=0}^{k_int-1} |X[j*k_int + i][k]|^2,  0 <= j < M // k_int
+
+    Spectra beyond the last whole group are not used.
+    """
+    k_int = int(k_int)
+    if k_int < 1:
+        raise ValueError("k_int must be >= 1")
+    spectra = ppf(x, h, n_channels, taps)
+    groups = spectra.shape[0] // k_int
+    power = np.abs(spectra[:groups * k_int]) ** 2
+    return power.reshape(groups, k_int, spectra.shape[1]).sum(axis=1)

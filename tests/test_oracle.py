@@ -238,9 +238,57 @@ def pin_p10_stream(mod):
     assert np.max(np.abs(streamed - batch)) <= 1e-12 * _rms(batch) * np.sqrt(n)
 
 
+def pin_p11_power_tone_exact(mod):
+    """Detected power of a bin-centred tone through one rectangular tap:
+    X[m][k0] = N A e^(i phi) in every spectrum, so each group of K spectra
+    holds K N^2 A^2 in bin k0 and nothing elsewhere."""
+    n, amp, phi, k0 = 64, 0.75, 0.4, 9
+    for k_int in (1, 3, 8):
+        m_total = 2 * k_int + 1                     # one spectrum beyond the last group
+        t = np.arange(m_total * n)
+        x = amp * np.exp(2j * np.pi * k0 * t / n + 1j * phi)
+        p = mod.ppf_power(x, np.ones(n), n, 1, k_int)
+        assert p.shape == (m_total // k_int, n)
+        want = k_int * n * n * amp * amp
+        assert np.allclose(p[:, k0], want, rtol=1e-12), (k_int, p[:, k0], want)
+        others = np.delete(p, k0, axis=1)
+        assert np.max(others) <= 1e-18 * want * n
+
+
+def pin_p12_power_parseval(mod):
+    """Per group, the summed power over bins is N times the presum energy of
+    its K spectra (Parseval), with the presum from the FIR step alone."""
+    rng = np.random.default_rng(12)
+    n, taps, k_int, m_total = 32, 4, 5, 17
+    x = rng.standard_normal((m_total + taps - 1) * n) + 1j * rng.standard_normal((m_total + taps - 1) * n)
+    h = rng.standard_normal(taps * n)
+    p = mod.ppf_power(x, h, n, taps, k_int)
+    u = mod.fir_presum(x, h, n, taps)
+    assert p.shape == (m_total // k_int, n)
+    for j in range(p.shape[0]):
+        energy = 0.0
+        for i in range(k_int):
+            energy += float(np.sum(np.abs(u[j * k_int + i]) ** 2))
+        assert np.isclose(p[j].sum(), n * energy, rtol=1e-10), j
+
+
+def pin_p13_power_noise_level(mod):
+    """White complex noise of variance 2 sigma^2 per sample: the expected
+    detected power of a bin is K N 2 sigma^2 sum_t h_c^2 averaged over c,
+    i.e. K * 2 sigma^2 * sum(h^2) per bin for the prototype normalised by
+    sum over all T*N taps."""
+    rng = np.random.default_rng(13)
+    n, taps, k_int, m_total, sigma = 128, 4, 4, 400, 1.5
+    x = sigma * (rng.standard_normal((m_total + taps - 1) * n) + 1j * rng.standard_normal((m_total + taps - 1) * n))
+    h = rng.uniform(0.5, 1.5, taps * n)
+    p = mod.ppf_power(x, h, n, taps, k_int)
+    expect = k_int * 2 * sigma * sigma * np.sum(h * h)       # per bin, averaged over channels (times N / N)
+    assert abs(p.mean() / expect - 1.0) < 0.02, p.mean() / expect
+
+
 PINS = [pin_p1_bruteforce, pin_p2_library_fft, pin_p3_impulse, pin_p4_single_segment,
         pin_p5_tone, pin_p6_linearity, pin_p7_parseval, pin_p8_hermitian, pin_p9_shift,
-        pin_p10_stream]
+        pin_p10_stream, pin_p11_power_tone_exact, pin_p12_power_parseval, pin_p13_power_noise_level]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
@@ -303,6 +351,10 @@ MUTANTS = {
     "stream_history_long": ("np.zeros((t_count - 1) * n", "np.zeros(t_count * n"),
     "spectra_count_off": ("return max(0, n_samples // n_channels - taps + 1)",
                           "return max(0, n_samples // n_channels - taps)"),
+    "power_not_squared": ("np.abs(spectra[:groups * k_int]) ** 2", "np.abs(spectra[:groups * k_int])"),
+    "power_mean_not_sum": (".sum(axis=1)\n", ".mean(axis=1)\n"),
+    "power_groups_shifted": ("spectra[:groups * k_int]", "spectra[1:groups * k_int + 1]"),
+    "power_group_short": ("groups = spectra.shape[0] // k_int", "groups = spectra.shape[0] // k_int\n    k_int = max(1, k_int - 1)"),
 }
 
 
