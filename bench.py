@@ -199,7 +199,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep", "mb"])
+                    choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep", "mb", "detect"])
+    ap.add_argument("--k-int", type=int, default=16, help="detect: spectra integrated per power spectrum")
     ap.add_argument("--load", type=float, default=50.0, help="serving: offered load in multiples of 6.5 GB/s")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
@@ -267,6 +268,48 @@ def main() -> int:
                                         "samples_per_s": round(n * m_total / (ms32 * 1e-3), 1),
                                         "path": {1: "fused", 2: "two_pass"}.get(used32)}
         print(json.dumps(rec), flush=True)
+        return 0
+
+    if args.workload == "detect":
+        # C2 with detection in the epilogue: |X|^2 summed over K spectra; the
+        # output shrinks from 8 B per bin and spectrum to 4 B per bin per K
+        cfg = WORKLOADS["c2"]
+        n, taps, k_int = cfg["N"], cfg["T"], args.k_int
+        m_total = (cfg["samples"] // n - taps + 1) // k_int * k_int
+        h32 = signals.design_coeffs(n, taps, cfg["window"]).astype(np.float32)
+        x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=cfg["seed"])
+        x_dev = torch.from_numpy(x).cuda()
+        del x
+        plan = ppf.Plan(n, taps, h32)
+        out = torch.empty((m_total // k_int, n), dtype=torch.float32, device="cuda")
+        stream = torch.cuda.current_stream()
+        ppf.ppf_set_stream(plan.handle, stream.cuda_stream)
+        for _ in range(args.warmup):
+            ppf.ppf_execute_power(plan.handle, x_dev, out, m_total, k_int)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            ppf.ppf_execute_power(plan.handle, x_dev, out, m_total, k_int)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        used = plan.path
+        plan.close()
+        in_b = metrics.input_bytes(n, m_total)
+        gbps = in_b / (ms * 1e-3) / 1e9
+        alg = (m_total + taps - 1) * n * 8 + (m_total // k_int) * n * 4 + taps * n * 4
+        peak = metrics.HBM_PEAK_BYTES_PER_S / 1e9
+        print(json.dumps({
+            "metric": METRIC, "value": round(gbps, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "realtime_multiple": round(metrics.realtime_multiple(gbps * 1e9), 2),
+            "config": {"workload": f"detect_k{k_int}_n1024_t8_2p27", "N": n, "taps": taps, "nspectra": m_total,
+                       "K": k_int, "path": {1: "fused", 2: "two_pass"}.get(used)},
+            "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 2), "peak": peak, "unit": "GB/s",
+                         "frac": round(alg / (ms * 1e-3) / 1e9 / peak, 4), "traffic": None,
+                         "algorithmic_bytes": alg}}), flush=True)
         return 0
 
     if args.workload == "mb":

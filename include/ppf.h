@@ -176,6 +176,21 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
 int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long long nspectra,
                      long long chunk_spectra);
 
+/*
+ * ppf_execute_power - detection after the filter bank: the power of every
+ * bin summed over K consecutive spectra (the screening step the filter bank
+ * feeds, section 1), computed in the transform's epilogue so the complex
+ * spectra never reach memory. Enqueued asynchronously on the plan's stream.
+ *
+ * in:        device pointer, (nspectra + T - 1) * N samples of the input type.
+ * out_power: device pointer, (nspectra / K) * N floats,
+ *            out_power[j*N + k] = sum_{i<K} |X[j*K + i][k]|^2.
+ * K >= 1 and nspectra a multiple of K (else PPF_ERR_INVALID). Alignment,
+ * overlap and nspectra rules as ppf_execute. Plans in the matrix-core mode
+ * return PPF_ERR_UNSUPPORTED.
+ */
+int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K);
+
 /* ppf_destroy - wait for the plan's stream, then free the plan. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);
 

@@ -162,9 +162,16 @@ struct ppf_stream_s {
 
 namespace {
 
-int ensure_workspace(ppf_plan_t p) {
-  if (p->d_ws) return PPF_OK;
+int ensure_workspace(ppf_plan_t p, long long min_spectra = 1) {
+  if (p->d_ws && p->chunk_spectra >= min_spectra) return PPF_OK;
+  if (p->d_ws) {   // grow: earlier work on the plan's stream may still read it
+    const hipError_t es = hipStreamSynchronize(p->stream);
+    if (es != hipSuccess) return fail_hip(es, "workspace synchronize");
+    hipFree(p->d_ws);
+    p->d_ws = nullptr;
+  }
   long long k = (long long)(kWorkspaceBytes / (8ull * p->N));
+  if (k < min_spectra) k = min_spectra;
   if (k < 1) k = 1;
   p->chunk_spectra = k;
   p->ws_bytes = (size_t)k * p->N * 8;
@@ -214,6 +221,32 @@ int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* 
     if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
     e = ppf::launch_fft(pd, p->d_ws, (char*)out + (size_t)c0 * pd.N * 8, k, p->stream);
     if (e != hipSuccess) return fail_hip(e, "FFT kernel launch");
+  }
+  return PPF_OK;
+}
+
+// Detection: |X|^2 summed over K spectra, M a multiple of K.
+int run_power(ppf_plan_t p, const void* in, float* pout, long long M, int K) {
+  const ppf::PlanDev pd = p->dev();
+  const size_t sb = (size_t)sample_bytes(p->in_type);
+  if (p->path == PPF_PATH_FUSED) {
+    ppf::BatchArgs a{in, in, 0, nullptr, M};
+    hipError_t e = ppf::launch_fused_power(pd, a, pout, K, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "fused power kernel launch");
+    return PPF_OK;
+  }
+  // two-pass: chunks of whole groups of K spectra
+  int st = ensure_workspace(p, K);
+  if (st != PPF_OK) return st;
+  const long long chunk = p->chunk_spectra / K * K;
+  for (long long c0 = 0; c0 < M; c0 += chunk) {
+    const long long k = (M - c0 < chunk) ? (M - c0) : chunk;
+    ppf::BatchArgs a{(const char*)in + (size_t)c0 * pd.N * sb, (const char*)in + (size_t)c0 * pd.N * sb, 0,
+                     p->d_ws, k};
+    hipError_t e = ppf::launch_fir(pd, a, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
+    e = ppf::launch_fft_power(pd, p->d_ws, pout + (size_t)(c0 / K) * pd.N, k, K, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "FFT power kernel launch");
   }
   return PPF_OK;
 }
@@ -470,6 +503,31 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra) 
     return st;
   } catch (...) {
     return fail(PPF_ERR_HIP, "unexpected exception in ppf_execute");
+  }
+}
+
+int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K) {
+  try {
+    if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+    if (K < 1) return fail(PPF_ERR_INVALID, "K=%d must be >= 1", K);
+    if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
+    if (nspectra % K) return fail(PPF_ERR_INVALID, "nspectra=%lld is not a multiple of K=%d", nspectra, K);
+    if (plan->fft_mode == PPF_FFT_MFMA_F16)
+      return fail(PPF_ERR_UNSUPPORTED, "detection is not built for the matrix-core mode");
+    if (nspectra == 0) { g_status = PPF_OK; return PPF_OK; }
+    if (!in || !out_power) return fail(PPF_ERR_INVALID, "in or out_power is NULL");
+    if (((uintptr_t)in & 15) || ((uintptr_t)out_power & 15))
+      return fail(PPF_ERR_ALIGN, "in and out_power must be 16-byte aligned");
+    const size_t sb = (size_t)sample_bytes(plan->in_type);
+    const size_t in_bytes = (size_t)(nspectra + plan->T - 1) * plan->N * sb;
+    const size_t out_bytes = (size_t)(nspectra / K) * plan->N * 4;
+    if (overlaps((uintptr_t)in, in_bytes, (uintptr_t)out_power, out_bytes))
+      return fail(PPF_ERR_INVALID, "in and out_power overlap");
+    const int st = run_power(plan, in, out_power, nspectra, K);
+    if (st == PPF_OK) g_status = PPF_OK;
+    return st;
+  } catch (...) {
+    return fail(PPF_ERR_NOMEM, "unexpected exception in ppf_execute_power");
   }
 }
 

@@ -93,6 +93,11 @@ hipError_t launch_history(const void* old_hist, const void* chunk, void* new_his
                           long long hist_samples, long long chunk_samples, int sample_bytes,
                           hipStream_t st);
 
+// Detection: |X|^2 summed over K consecutive spectra (M a multiple of K),
+// written to pout as (M / K) x N floats instead of the spectra.
+hipError_t launch_fused_power(const PlanDev& pd, const BatchArgs& a, float* pout, int K, hipStream_t st);
+hipError_t launch_fft_power(const PlanDev& pd, const void* in, float* pout, long long M, int K, hipStream_t st);
+
 // Reduced-precision fused kernel with matrix-core DFT stages (N = 4096,
 // complex int8 input, FP16 coefficients).
 struct MfmaDev {

@@ -26,588 +26,9 @@
 // with a per-thread register ring writes u to a workspace, then the same
 // fused kernel with one identity tap performs the FFTs.
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "ppf_internal.h"
+#include "ppf_engine.h"
 
 namespace ppf {
-
-typedef float v2f __attribute__((ext_vector_type(2)));
-
-// --------------------------------------------------------------------------
-// complex helpers
-// --------------------------------------------------------------------------
-
-__device__ __forceinline__ v2f cadd(v2f a, v2f b) { v2f r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-__device__ __forceinline__ v2f csub(v2f a, v2f b) { v2f r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-// a * w (complex)
-__device__ __forceinline__ v2f cmul(v2f a, v2f w) {
-  v2f r;
-  r.x = fmaf(a.x, w.x, -(a.y * w.y));
-  r.y = fmaf(a.x, w.y, a.y * w.x);
-  return r;
-}
-// a * (-i)
-__device__ __forceinline__ v2f mul_mi(v2f a) { v2f r; r.x = a.y; r.y = -a.x; return r; }
-// a * (c - i s) for a compile-time root of unity
-__device__ __forceinline__ v2f mul_cs(v2f a, float c, float s) {
-  v2f r;
-  r.x = fmaf(a.x, c, a.y * s);
-  r.y = fmaf(a.y, c, -(a.x * s));
-  return r;
-}
-
-// exp(-2 pi i p/16) * a for compile-time p (0 <= p < 16)
-template <int P>
-__device__ __forceinline__ v2f w16(v2f a) {
-  constexpr int p = P & 15;
-  constexpr float C1 = 0.92387953251128674f;  // cos(pi/8)
-  constexpr float S1 = 0.38268343236508978f;  // sin(pi/8)
-  constexpr float H = 0.70710678118654752f;   // sqrt(2)/2
-  if constexpr (p == 0) return a;
-  else if constexpr (p == 4) return mul_mi(a);
-  else if constexpr (p == 8) { v2f r; r.x = -a.x; r.y = -a.y; return r; }
-  else if constexpr (p == 12) { v2f r; r.x = -a.y; r.y = a.x; return r; }
-  else if constexpr (p == 2) { v2f r; r.x = (a.x + a.y) * H; r.y = (a.y - a.x) * H; return r; }
-  else if constexpr (p == 6) { v2f r; r.x = (a.y - a.x) * H; r.y = -(a.x + a.y) * H; return r; }
-  else if constexpr (p == 10) { v2f r; r.x = -(a.x + a.y) * H; r.y = (a.x - a.y) * H; return r; }
-  else if constexpr (p == 14) { v2f r; r.x = (a.x - a.y) * H; r.y = (a.x + a.y) * H; return r; }
-  else if constexpr (p == 1) return mul_cs(a, C1, S1);
-  else if constexpr (p == 3) return mul_cs(a, S1, C1);
-  else if constexpr (p == 5) return mul_cs(a, -S1, C1);
-  else if constexpr (p == 7) return mul_cs(a, -C1, S1);
-  else if constexpr (p == 9) return mul_cs(a, -C1, -S1);
-  else if constexpr (p == 11) return mul_cs(a, -S1, -C1);
-  else if constexpr (p == 13) return mul_cs(a, S1, -C1);
-  else return mul_cs(a, C1, -S1);  // p == 15
-}
-
-// --------------------------------------------------------------------------
-// small forward DFTs on registers: a[k] <- sum_n a[n] exp(-2 pi i nk/r)
-// --------------------------------------------------------------------------
-
-__device__ __forceinline__ void dft2(v2f& a0, v2f& a1) {
-  v2f t = a0;
-  a0 = cadd(t, a1);
-  a1 = csub(t, a1);
-}
-
-__device__ __forceinline__ void dft4(v2f& a0, v2f& a1, v2f& a2, v2f& a3) {
-  v2f t0 = cadd(a0, a2), t1 = csub(a0, a2);
-  v2f t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
-  a0 = cadd(t0, t2);
-  a2 = csub(t0, t2);
-  a1 = cadd(t1, t3);
-  a3 = csub(t1, t3);
-}
-
-template <int r>
-__device__ __forceinline__ void dft(v2f (&a)[r]) {
-  if constexpr (r == 1) {
-  } else if constexpr (r == 2) {
-    dft2(a[0], a[1]);
-  } else if constexpr (r == 4) {
-    dft4(a[0], a[1], a[2], a[3]);
-  } else if constexpr (r == 8) {
-    // even/odd split: X[k] = E[k] + W8^k O[k], X[k+4] = E[k] - W8^k O[k]
-    dft4(a[0], a[2], a[4], a[6]);
-    dft4(a[1], a[3], a[5], a[7]);
-    v2f o1 = w16<2>(a[3]), o2 = w16<4>(a[5]), o3 = w16<6>(a[7]);
-    v2f e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
-    a[0] = cadd(e0, a[1]); a[4] = csub(e0, a[1]);
-    a[1] = cadd(e1, o1);   a[5] = csub(e1, o1);
-    a[2] = cadd(e2, o2);   a[6] = csub(e2, o2);
-    a[3] = cadd(e3, o3);   a[7] = csub(e3, o3);
-  } else if constexpr (r == 16) {
-    // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
-    v2f y[4][4];
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
-      v2f b0 = a[n2], b1 = a[4 + n2], b2 = a[8 + n2], b3 = a[12 + n2];
-      dft4(b0, b1, b2, b3);
-      y[n2][0] = b0; y[n2][1] = b1; y[n2][2] = b2; y[n2][3] = b3;
-    }
-    y[1][1] = w16<1>(y[1][1]); y[1][2] = w16<2>(y[1][2]); y[1][3] = w16<3>(y[1][3]);
-    y[2][1] = w16<2>(y[2][1]); y[2][2] = w16<4>(y[2][2]); y[2][3] = w16<6>(y[2][3]);
-    y[3][1] = w16<3>(y[3][1]); y[3][2] = w16<6>(y[3][2]); y[3][3] = w16<9>(y[3][3]);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-      v2f b0 = y[0][k1], b1 = y[1][k1], b2 = y[2][k1], b3 = y[3][k1];
-      dft4(b0, b1, b2, b3);
-      a[k1] = b0; a[k1 + 4] = b1; a[k1 + 8] = b2; a[k1 + 12] = b3;
-    }
-  } else {
-    static_assert(r == 1 || r == 2 || r == 4 || r == 8 || r == 16, "unsupported radix");
-  }
-}
-
-// --------------------------------------------------------------------------
-// Stockham stage plan (compile time). Stage s has radix r_s (R while R
-// points remain, then the power-of-two remainder) and span Ns = prod r_<s.
-// Butterfly b (0 <= b < N/r) reads elements b + q*N/r and writes
-// (b/Ns)*Ns*r + b%Ns + q*Ns after the twiddle exp(-2 pi i (b%Ns) q/(Ns r)).
-// --------------------------------------------------------------------------
-
-// RX is the largest radix used (a divisor of R); a thread holding R
-// elements performs R/r butterflies of radix r per stage.
-constexpr int radix_at(int N, int RX, int s) {
-  int n = 1;
-  for (int i = 0; i < s; ++i) n *= (N / n >= RX ? RX : N / n);
-  return N / n >= RX ? RX : N / n;
-}
-constexpr int ns_at(int N, int RX, int s) {
-  int n = 1;
-  for (int i = 0; i < s; ++i) n *= radix_at(N, RX, i);
-  return n;
-}
-constexpr int num_stages(int N, int RX) {
-  int n = 1, s = 0;
-  while (n < N) { n *= (N / n >= RX ? RX : N / n); ++s; }
-  return s;
-}
-// twiddles a thread keeps for stage s: butterflies j + i*W share b % Ns
-// when Ns <= W, so one set serves all of them
-constexpr int tw_count(int N, int R, int RX, int s) {
-  if (s == 0) return 0;
-  const int r = radix_at(N, RX, s), Ns = ns_at(N, RX, s), W = N / R;
-  return (Ns <= W ? 1 : R / r) * (r - 1);
-}
-constexpr int tw_offset(int N, int R, int RX, int s) {
-  int o = 0;
-  for (int i = 0; i < s; ++i) o += tw_count(N, R, RX, i);
-  return o;
-}
-constexpr int tw_total(int N, int R, int RX) { return tw_offset(N, R, RX, num_stages(N, RX)); }
-
-// LDS word address of element i of a plane. gfx950 LDS has 64 four-byte
-// banks serving a whole wave per access. For N >= 256 (one group per wave)
-// element i goes to i XOR a mask of its 64-word row that spreads the row
-// index over bits 0-5 (row ^ row<<2 ^ row<<4): contiguous reads stay one
-// row, and the strided Stockham writes, whose lanes fall in rows with
-// different low row bits but fixed low offset bits, land in distinct banks.
-// Smaller N (several groups per wave) pad one word per 32 and shift group
-// planes by W words.
-template <int N>
-__device__ __forceinline__ int lds_index(int i) {
-  if constexpr (N >= 8192) {
-    // plain layout: every stage's addresses are one per-thread base plus
-    // immediates, which keeps 16 elements per thread within the registers
-    return i;
-  } else if constexpr (N >= 256) {
-    const int row = i >> 6;
-    return i ^ ((row ^ (row << 2) ^ (row << 4)) & 63);
-  } else {
-    return i + (i >> 5);
-  }
-}
-constexpr int plane_floats(int N, int W) {
-  if (N >= 8192) return N;
-  if (N >= 256) return N;
-  const int p = N + N / 32;
-  return W < 32 ? ((p + 31) / 32) * 32 + W : p;
-}
-
-// --------------------------------------------------------------------------
-// Per-group FFT through LDS
-// --------------------------------------------------------------------------
-
-// B spectra go through the stages together: they share every barrier and
-// twiddle, and give each wave independent work between barriers.
-template <int N, int R, int RX, int G, int B, bool DB, bool TWG>
-struct GroupFft {
-  static constexpr int W = N / R;
-  static constexpr int L = num_stages(N, RX);
-  static constexpr int PL = plane_floats(N, W);      // floats per plane
-  static constexpr int NBUF = DB ? 2 : 1;
-  static constexpr int NTW = TWG ? 1 : (tw_total(N, R, RX) > 0 ? tw_total(N, R, RX) : 1);
-  static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
-
-  float* lds;      // shared memory base of the block
-  int grp, j;
-  int par;         // buffer of the next exchange (double-buffered mode)
-  const v2f* tw;   // twiddle table (global)
-  v2f twr[NTW];
-
-  __device__ __forceinline__ float* plane(int buf, int b, int reim) const {
-    return lds + (((buf * B + b) * 2 + reim) * G + grp) * PL;
-  }
-
-  template <int S>
-  __device__ __forceinline__ void load_stage_tw() {
-    if constexpr (S < L) {
-      if constexpr (S > 0) {
-        constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
-        constexpr int nset = (Ns <= W) ? 1 : R / r;
-        constexpr int off = tw_offset(N, R, RX, S);
-        constexpr int step = N / (Ns * r);
-#pragma unroll
-        for (int ib = 0; ib < nset; ++ib) {
-          const int k = (j + ib * W) % Ns;
-#pragma unroll
-          for (int q = 1; q < r; ++q) twr[off + ib * (r - 1) + q - 1] = tw[k * q * step];
-        }
-      }
-      load_stage_tw<S + 1>();
-    }
-  }
-
-  __device__ __forceinline__ void init(float* smem, int grp_, int j_, const v2f* tw_) {
-    lds = smem; grp = grp_; j = j_; par = 0; tw = tw_;
-    if constexpr (!TWG) load_stage_tw<1>();
-  }
-
-  template <int S>
-  __device__ __forceinline__ v2f twiddle(int i, int q) const {
-    constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
-    if constexpr (TWG) {
-      // read at the point of use: the address is loop-invariant, and a
-      // hoisted load would keep every stage's twiddles live in registers;
-      // an opaque zero ties the load to this stage
-      int z;
-      asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-      const int k = (j + i * W) % Ns;
-      return tw[k * q * (N / (Ns * r)) + z];
-    } else {
-      const int ib = (Ns <= W) ? 0 : i;
-      return twr[tw_offset(N, R, RX, S) + ib * (r - 1) + q - 1];
-    }
-  }
-
-  template <int S>
-  __device__ __forceinline__ void stage(v2f (&v)[B][R]) {
-    constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
-    constexpr int nb = R / r;
-    if constexpr (S > 0) {
-      const int buf = DB ? par : 0;
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const float* re = plane(buf, b, 0);
-        const float* im = plane(buf, b, 1);
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-          const int idx = lds_index<N>(j + e * W);
-          v[b][e].x = re[idx];
-          v[b][e].y = im[idx];
-        }
-      }
-      if constexpr (DB) par ^= 1;
-#pragma unroll
-      for (int i = 0; i < nb; ++i)
-#pragma unroll
-        for (int q = 1; q < r; ++q) {
-          const v2f w = twiddle<S>(i, q);
-#pragma unroll
-          for (int b = 0; b < B; ++b) v[b][i + q * nb] = cmul(v[b][i + q * nb], w);
-        }
-    }
-    if constexpr (S == L - 1) {
-#pragma unroll
-      for (int b = 0; b < B; ++b)
-#pragma unroll
-        for (int i = 0; i < nb; ++i) {
-          v2f t[r];
-#pragma unroll
-          for (int q = 0; q < r; ++q) t[q] = v[b][i + q * nb];
-          dft<r>(t);
-#pragma unroll
-          for (int q = 0; q < r; ++q) v[b][i + q * nb] = t[q];
-        }
-    } else {
-      if constexpr (!DB) __syncthreads();   // earlier reads of the single buffer are done
-      const int buf = DB ? par : 0;
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        float* re = plane(buf, b, 0);
-        float* im = plane(buf, b, 1);
-#pragma unroll
-        for (int i = 0; i < nb; ++i) {
-          v2f t[r];
-#pragma unroll
-          for (int q = 0; q < r; ++q) t[q] = v[b][i + q * nb];
-          dft<r>(t);
-          const int bf = j + i * W;
-          const int base = (bf / Ns) * Ns * r + (bf % Ns);
-#pragma unroll
-          for (int q = 0; q < r; ++q) {
-            const int idx = lds_index<N>(base + q * Ns);
-            re[idx] = t[q].x;
-            im[idx] = t[q].y;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  template <int S>
-  __device__ __forceinline__ void run_from(v2f (&v)[B][R]) {
-    if constexpr (S < L) {
-      stage<S>(v);
-      run_from<S + 1>(v);
-    }
-  }
-
-  // in: v[b][e] = u_b[j + e*W]; out: v[b][e] = X_b[j + e*W]
-  __device__ __forceinline__ void run(v2f (&v)[B][R]) { run_from<0>(v); }
-};
-
-// --------------------------------------------------------------------------
-// block index -> tile: hardware hands consecutive workgroups to the 8 XCDs
-// in turn; give each XCD a contiguous range of tiles so neighbouring tiles,
-// which share tap-window blocks, meet in the same L2.
-// --------------------------------------------------------------------------
-
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  const int q = nblocks >> 3, rem = nblocks & 7;
-  const int xcd = bid & 7, k = bid >> 3;
-  return xcd * q + (xcd < rem ? xcd : rem) + k;
-}
-
-// --------------------------------------------------------------------------
-// fused FIR + FFT kernel
-// --------------------------------------------------------------------------
-
-// Input blocks are streamed with non-temporal loads unless disabled at
-// build time (measured faster on MI355X for the one-pass batch).
-#ifndef PPF_NT_LOADS
-#define PPF_NT_LOADS 1
-#endif
-constexpr bool kNtLoads = PPF_NT_LOADS != 0;
-
-// Raw buffer access (gfx9 descriptor): a scalar resource per block of N
-// samples, a 32-bit per-thread offset, and each element's extra offset as
-// a scalar constant. Reads outside the block's range return zero.
-constexpr int kBufDword3 = 0x00020000;
-constexpr int kAuxNt = 2;   // non-temporal cache policy bit of buffer instructions
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, kBufDword3);
-}
-template <int AUX>
-__device__ __forceinline__ v2f buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
-}
-template <int AUX>
-__device__ __forceinline__ void buf_store(v2f v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
-                                        r, voff, soff, AUX);
-}
-
-// Block and spectrum indices of one launch fit in 32 bits (the host splits
-// larger batches), so their arithmetic and compares stay on the scalar unit.
-struct FusedParams {
-  const v2f* x0;       // first input segment (h0 blocks)
-  const v2f* x1;       // second input segment
-  v2f* out;
-  const float* coef;   // TP*N
-  const v2f* tw;       // N twiddles
-  int h0;
-  int M;               // spectra
-  int S;               // spectra per group tile
-  int d;               // leading zero tap segments (TP - T)
-  int nblocks;
-};
-
-// One tile of spectra: the input is the concatenation x0 (h0 blocks) ++ x1
-// (h01 - h0 blocks) ++ x2, spectrum m of the tile reads blocks m .. m+T-1
-// of it and is written to out + m*N.
-struct TileArgs {
-  const v2f* x0;
-  const v2f* x1;
-  const v2f* x2;
-  v2f* out;
-  int h0;
-  int h01;
-};
-
-template <int N>
-__device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
-  return rb < a.h0 ? a.x0 + (long long)rb * N
-                   : (rb < a.h01 ? a.x1 + (long long)(rb - a.h0) * N : a.x2 + (long long)(rb - a.h01) * N);
-}
-
-// Per-block engine of the fused kernel: coefficients, twiddles and lane
-// offsets are loaded once and reused by every tile the block processes.
-//
-// Ring of Q = TP + PF blocks; slot s always holds a block whose index is
-// s modulo Q (counted from the tile start). B spectra are computed per
-// step; the B blocks loaded at a step replace the B oldest, which no later
-// spectrum needs, so any Q >= TP + B - 1 is hazard-free and PF - B + 1
-// blocks of each step are loads running ahead.
-// UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
-// presum is the loaded block itself and no coefficients are held.
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
-struct FusedEngine {
-  static constexpr int W = N / R;
-  static constexpr int Q = TP + PF;
-  static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
-  static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
-  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
-
-  Fft fft;
-  int j;
-  int d;
-  float hreg[UNIT ? 1 : TP][R];
-  uint32_t loff;       // byte offset of channel j inside a block; element e adds e*W*8
-
-  __device__ __forceinline__ void init(float* smem, int grp, int j_, const float* coef, const v2f* tw, int d_) {
-    j = j_;
-    d = d_;
-    fft.init(smem, grp, j, tw);
-    if constexpr (!UNIT) {
-#pragma unroll
-      for (int t = 0; t < TP; ++t)
-#pragma unroll
-        for (int e = 0; e < R; ++e) hreg[t][e] = coef[t * N + j + e * W];
-    }
-    loff = (uint32_t)j * (uint32_t)sizeof(v2f);
-  }
-
-  // Spectra m0 .. m0+ng-1 of the tile; niter >= ng is the same for every
-  // group of the block (barriers), extra steps compute but store nothing.
-  __device__ __forceinline__ void run(const TileArgs& a, int m0, int ng, int niter) {
-    // virtual blocks this group reads: [vb_lo, vb_hi). Below vb_lo the taps
-    // are the zero padding; at or above vb_hi only spectra beyond the tile
-    // would use them. Those slots are not loaded.
-    const int vb_lo = m0 > d ? m0 : d;
-    const int vb_hi = ng > 0 ? m0 + ng + TP - 1 : m0;
-
-    // zero start: a slot that is never loaded holds a finite value, so a
-    // zero padding tap times it is exactly zero
-    v2f ring[Q][R];
-#pragma unroll
-    for (int s = 0; s < Q; ++s)
-#pragma unroll
-      for (int e = 0; e < R; ++e) { ring[s][e].x = 0.f; ring[s][e].y = 0.f; }
-    auto load = [&](v2f (&dst)[R], int vb) {
-      if (vb >= vb_lo && vb < vb_hi) {
-        if constexpr (G == 1) {
-          const __amdgpu_buffer_rsrc_t rs = block_rsrc(block_ptr<N>(a, vb - d), N * (int)sizeof(v2f));
-#pragma unroll
-          for (int e = 0; e < R; ++e)
-            dst[e] = buf_load<kNtLoads ? kAuxNt : 0>(rs, loff, (uint32_t)(e * W * (int)sizeof(v2f)));
-        } else {
-          const v2f* src = block_ptr<N>(a, vb - d) + j;
-#pragma unroll
-          for (int e = 0; e < R; ++e) dst[e] = src[e * W];
-        }
-      }
-    };
-
-#pragma unroll
-    for (int s = 0; s < Q - B; ++s) load(ring[s], m0 + s);
-
-    for (int base = 0; base < niter; base += Q) {
-#pragma unroll
-      for (int k = 0; k < Q; k += B) {
-        const int it = base + k;
-        if (it >= niter) break;
-#pragma unroll
-        for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
-        v2f v[B][R];
-#pragma unroll
-        for (int b = 0; b < B; ++b)
-#pragma unroll
-          for (int e = 0; e < R; ++e) {
-            if constexpr (UNIT) {
-              v[b][e] = ring[(k + b) % Q][e];
-            } else {
-              v2f acc;
-              acc.x = hreg[0][e] * ring[(k + b) % Q][e].x;
-              acc.y = hreg[0][e] * ring[(k + b) % Q][e].y;
-#pragma unroll
-              for (int t = 1; t < TP; ++t) {
-                acc.x = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].x, acc.x);
-                acc.y = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].y, acc.y);
-              }
-              v[b][e] = acc;
-            }
-          }
-        fft.run(v);
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-          if (it + b < ng) {
-            if constexpr (G == 1) {
-              const __amdgpu_buffer_rsrc_t rs =
-                  block_rsrc(a.out + (long long)(m0 + it + b) * N, N * (int)sizeof(v2f));
-#pragma unroll
-              for (int e = 0; e < R; ++e) buf_store<kAuxNt>(v[b][e], rs, loff, (uint32_t)(e * W * (int)sizeof(v2f)));
-            } else {
-              v2f* dst = a.out + (long long)(m0 + it + b) * N + j;
-#pragma unroll
-              for (int e = 0; e < R; ++e) __builtin_nontemporal_store(v[b][e], dst + e * W);
-            }
-          }
-        }
-      }
-    }
-  }
-};
-
-// Batch form: a wave of tiles of S consecutive spectra covers the batch;
-// group g of block lb owns the tile (lb*G + g).
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
-__global__ void __launch_bounds__((N / R) * G)
-ppf_fused_kernel(FusedParams p) {
-  constexpr int W = N / R;
-  extern __shared__ float smem[];
-  const int tid = threadIdx.x;
-  const int grp = (G == 1) ? 0 : tid / W;
-  const int j = (G == 1) ? tid : tid % W;
-  const int lb = xcd_remap(blockIdx.x, p.nblocks);
-  const int blk_m0 = lb * G * p.S;
-  if (blk_m0 >= p.M) return;                                   // whole block idle
-  const int m0 = blk_m0 + grp * p.S;
-  const int rem = p.M - m0;
-  const int ng = rem <= 0 ? 0 : (rem < p.S ? rem : p.S);       // this group's spectra
-  const int brem = p.M - blk_m0;
-  const int niter = brem < p.S ? brem : p.S;                   // uniform over the block
-
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT> eng;
-  eng.init(smem, grp, j, p.coef, p.tw, p.d);
-  TileArgs a{p.x0, p.x1, p.x1, p.out, p.h0, p.h0};
-  eng.run(a, m0, ng, niter);
-}
-
-// Descriptor form (serving): the tiles are listed in device memory; a
-// persistent grid walks them, G tiles per block at a time. Every wave of a
-// block exits at the same tile index, after the same number of barriers.
-
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
-__global__ void __launch_bounds__((N / R) * G)
-ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, const v2f* tw, int d) {
-  constexpr int W = N / R;
-  extern __shared__ float smem[];
-  __shared__ int s_count[G];
-  const int tid = threadIdx.x;
-  const int grp = (G == 1) ? 0 : tid / W;
-  const int j = (G == 1) ? tid : tid % W;
-  const int first = cls->first;
-  const int ntiles = cls->ntiles;
-  if ((int)blockIdx.x * G >= ntiles) return;                  // whole block idle
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT> eng;
-  eng.init(smem, grp, j, coef, tw, d);
-  for (int t0 = blockIdx.x * G; t0 < ntiles; t0 += gridDim.x * G) {
-    const int t = t0 + grp;
-    TileArgs a{nullptr, nullptr, nullptr, nullptr, 0, 0};
-    int count = 0;
-    if (t < ntiles) {
-      const TileDesc& td = tiles[first + t];
-      a = TileArgs{(const v2f*)td.x0, (const v2f*)td.x1, (const v2f*)td.x2, (v2f*)td.out, td.h0, td.h0 + td.h1};
-      count = td.count;
-    }
-    int niter = count;
-    if constexpr (G > 1) {
-      if (j == 0) s_count[grp] = count;
-      __syncthreads();
-      niter = 0;
-#pragma unroll
-      for (int g = 0; g < G; ++g) niter = s_count[g] > niter ? s_count[g] : niter;
-      __syncthreads();
-    }
-    eng.run(a, 0, count, niter);
-  }
-}
 
 // --------------------------------------------------------------------------
 // FIR-only kernel (two-pass form): one channel per thread, register ring
@@ -798,141 +219,6 @@ __global__ void __launch_bounds__(256) ppf_history_desc_kernel(const int* count,
   }
 }
 
-// --------------------------------------------------------------------------
-// configurations and dispatch
-// --------------------------------------------------------------------------
-
-// Build-time override of the prefetch depth of the fused kernels (tuning).
-#ifndef PPF_PF_FUSED_OVERRIDE
-#define PPF_PF_FUSED_OVERRIDE 0
-#endif
-
-// elements per thread R and groups per block G for the FFT of N points
-constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : 16); }
-constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
-constexpr int cfg_W(int N) { return N / cfg_R(N); }
-constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
-constexpr int cfg_PF(int N, int TP) {
-  return TP == 1 ? (N >= 16384 ? 0 : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
-                 : (N >= 2048 ? 2 : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
-}
-constexpr bool cfg_TWG(int N) { return N >= 16384; }
-// spectra per FFT pass (build-time tuning; 4 measured best at N=1024, T=8)
-#ifndef PPF_BATCH_OVERRIDE
-#define PPF_BATCH_OVERRIDE 4
-#endif
-constexpr bool batch_fits(int N, int TP, int B) {
-  return (TP + cfg_PF(N, TP)) % B == 0 && TP + cfg_PF(N, TP) >= TP + B - 1;
-}
-constexpr int cfg_B(int N, int TP) {
-  // with 16 taps the ring already fills the register file
-  return PPF_BATCH_OVERRIDE > 1 && TP <= 8 && batch_fits(N, TP, PPF_BATCH_OVERRIDE) ? PPF_BATCH_OVERRIDE : 1;
-}
-constexpr bool cfg_DB(int N, int B) {
-  return 2ull * B * 2 * cfg_G(N) * plane_floats(N, cfg_W(N)) * sizeof(float) <= 80 * 1024;
-}
-
-struct KernelInfo {
-  const void* fn;
-  int block;
-  int G;
-  size_t lds;
-};
-
-static int device_cus() {
-  static const int cus = [] {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
-    return n;
-  }();
-  return cus;
-}
-
-static int occupancy(const KernelInfo& ki) {
-  int occ = 0;
-  if (ki.lds > 64 * 1024) hipFuncSetAttribute(ki.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ki.lds);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ki.fn, ki.block, ki.lds) != hipSuccess || occ <= 0) occ = 1;
-  return occ;
-}
-
-template <int N, int TP, bool UNIT>
-static const KernelInfo& fused_info() {
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
-  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>,
-                             (N / R) * G, G, Fft::lds_bytes()};
-  return ki;
-}
-
-// Largest number of spectra in one launch: block and spectrum indices stay
-// below 2^31 inside the kernels.
-constexpr long long kMaxLaunchSpectra = 1ll << 28;
-
-// Part [s0, s0+k) of a batch: the concatenated input starts at block s0.
-static BatchArgs sub_batch(const BatchArgs& a, int N, size_t sample_bytes, long long s0, long long k) {
-  BatchArgs o;
-  if (s0 < a.h0) {
-    o.x0 = (const char*)a.x0 + (size_t)s0 * N * sample_bytes;
-    o.h0 = a.h0 - s0;
-    o.x1 = a.x1;
-  } else {
-    o.x0 = a.x1;
-    o.h0 = 0;
-    o.x1 = (const char*)a.x1 + (size_t)(s0 - a.h0) * N * sample_bytes;
-  }
-  o.out = (char*)a.out + (size_t)s0 * N * 8;
-  o.M = k;
-  return o;
-}
-
-template <int N, int TP, bool UNIT>
-static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const float* coef, int T,
-                                   hipStream_t st) {
-  const KernelInfo& ki = fused_info<N, TP, UNIT>();
-  static const int occ = occupancy(ki);
-  const long long resident_groups = (long long)device_cus() * occ * ki.G;
-  long long S = (a.M + resident_groups - 1) / resident_groups;
-  if (S < 2 * TP) S = 2 * TP;                                  // bound the tap-window re-reads
-  const long long groups = (a.M + S - 1) / S;
-  const long long nblocks = (groups + ki.G - 1) / ki.G;
-  if (nblocks <= 0) return hipSuccess;
-  FusedParams p;
-  p.x0 = (const v2f*)a.x0;
-  p.x1 = (const v2f*)a.x1;
-  p.out = (v2f*)a.out;
-  p.coef = coef;
-  p.tw = (const v2f*)pd.tw;
-  p.h0 = (int)a.h0;
-  p.M = (int)a.M;
-  p.S = (int)S;
-  p.d = TP - T;
-  p.nblocks = (int)nblocks;
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>), dim3((unsigned)nblocks), dim3(ki.block),
-                     ki.lds, st, p);
-  return hipGetLastError();
-}
-
-template <int N, int TP, bool UNIT = false>
-static hipError_t fused_launch(const PlanDev& pd, const BatchArgs& a, const float* coef, int T, hipStream_t st) {
-  for (long long s0 = 0; s0 < a.M; s0 += kMaxLaunchSpectra) {
-    const long long k = a.M - s0 < kMaxLaunchSpectra ? a.M - s0 : kMaxLaunchSpectra;
-    const hipError_t e = fused_launch_one<N, TP, UNIT>(pd, sub_batch(a, N, 8, s0, k), coef, T, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-typedef hipError_t (*FusedFn)(const PlanDev&, const BatchArgs&, const float*, int, hipStream_t);
-
-// The fused path exists where the tap window of a thread (R channels x TP
-// taps, plus coefficients) fits the register file at useful occupancy.
-constexpr bool fused_ok(int N, int TP) {
-  return TP == 1 || (N <= 1024 && TP <= 16) || (N == 2048 && TP <= 8);
-}
 
 template <int N>
 static FusedFn fused_for_taps(int TP) {
@@ -976,7 +262,7 @@ bool fft_available(int N) { return fused_fn(N, 1) != nullptr; }
 hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
   FusedFn f = fused_fn(pd.N, pd.TP);
   if (!f) return hipErrorInvalidValue;
-  return f(pd, a, pd.coef, pd.T, st);
+  return f(pd, a, pd.coef, pd.T, st, nullptr, 1);
 }
 
 static FusedFn fft_fn(int N) {
@@ -1000,7 +286,7 @@ hipError_t launch_fft(const PlanDev& pd, const void* in, void* out, long long M,
   FusedFn f = fft_fn(pd.N);
   if (!f) return hipErrorInvalidValue;
   BatchArgs a{in, in, 0, out, M};
-  return f(pd, a, pd.ones, 1, st);
+  return f(pd, a, pd.ones, 1, st, nullptr, 1);
 }
 
 template <int TP, int IT>

@@ -69,6 +69,7 @@ _SIGNATURES = [
     ("ppf_plan_query", _c_int, [_c_vp, _c_int, ctypes.POINTER(_c_ll)]),
     ("ppf_execute", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
     ("ppf_execute_host", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_ll]),
+    ("ppf_execute_power", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_int]),
     ("ppf_destroy", _c_int, [_c_vp]),
     ("ppf_stream_create", _c_vp, [_c_vp]),
     ("ppf_stream_push", _c_int, [_c_vp, _c_vp]),
@@ -192,6 +193,10 @@ def ppf_execute(plan: int, inp, out, nspectra: int) -> int:
 
 def ppf_execute_host(plan: int, host_in, host_out, nspectra: int, chunk_spectra: int = 0) -> int:
     return _check(lib().ppf_execute_host(plan, _addr(host_in), _addr(host_out), int(nspectra), int(chunk_spectra)))
+
+
+def ppf_execute_power(plan: int, inp, out_power, nspectra: int, k_int: int) -> int:
+    return _check(lib().ppf_execute_power(plan, _addr(inp), _addr(out_power), int(nspectra), int(k_int)))
 
 
 def ppf_destroy(plan: int) -> int:
@@ -328,6 +333,19 @@ class Plan:
         st = torch.cuda.current_stream(x.device) if stream is None else stream
         ppf_set_stream(self.handle, st.cuda_stream)
         ppf_execute(self.handle, x, out, nspectra)
+        return out
+
+    def execute_power(self, x, k_int: int, out=None, nspectra: int | None = None, stream=None):
+        """Detected power |X|^2 summed over k_int spectra: (M // k_int, N) float32."""
+        import torch
+        if nspectra is None:
+            samples = x.numel() if x.is_complex() else x.shape[0]
+            nspectra = samples // self.N - self.T + 1
+        if out is None:
+            out = torch.empty((nspectra // k_int, self.N), dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(x.device) if stream is None else stream
+        ppf_set_stream(self.handle, st.cuda_stream)
+        ppf_execute_power(self.handle, x, out, nspectra, k_int)
         return out
 
     def execute_host(self, x, out, nspectra: int | None = None, chunk_spectra: int = 0, stream=None):
