@@ -426,23 +426,47 @@ struct FusedEngine {
   static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
 
+  // Long tap windows keep their coefficients in LDS (TP x N floats after
+  // the FFT planes, shared by the groups of the block) instead of TP x R
+  // registers per thread, which would leave one wave per SIMD.
+  static constexpr bool CL = !UNIT && TP >= 16;
+  static constexpr size_t coef_lds_bytes() { return CL ? (size_t)TP * N * sizeof(float) : 0; }
+  static constexpr size_t lds_bytes() { return Fft::lds_bytes() + coef_lds_bytes(); }
+
   Fft fft;
   int j;
   int d;
-  float hreg[UNIT ? 1 : TP][R];
+  float hreg[(UNIT || CL) ? 1 : TP][R];
+  uint32_t hl;         // CL: LDS byte address of this thread's coefficient column
   uint32_t loff;       // byte offset of channel j inside a block; element e adds e*W*8
 
   __device__ __forceinline__ void init(float* smem, int grp, int j_, const float* coef, const v2f* tw, int d_) {
     j = j_;
     d = d_;
     fft.init(smem, grp, j, tw);
-    if constexpr (!UNIT) {
+    if constexpr (CL) {
+      float* cl = (float*)((char*)smem + Fft::lds_bytes());
+      for (int i = threadIdx.x; i < TP * N; i += blockDim.x) cl[i] = coef[i];
+      __syncthreads();
+      hl = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float*)(cl + j);
+    } else if constexpr (!UNIT) {
 #pragma unroll
       for (int t = 0; t < TP; ++t)
 #pragma unroll
         for (int e = 0; e < R; ++e) hreg[t][e] = coef[t * N + j + e * W];
     }
     loff = (uint32_t)j * (uint32_t)sizeof(v2f);
+  }
+
+  // coefficient of tap t, element e; CL reads LDS through a base the caller
+  // refreshes every step (so the reads are not hoisted into registers)
+  __device__ __forceinline__ float hcoef(uint32_t base, int t, int e) const {
+    if constexpr (CL) {
+      return *(const __attribute__((address_space(3))) float*)(uintptr_t)(base + (uint32_t)((t * N + e * W) *
+                                                                                           (int)sizeof(float)));
+    } else {
+      return hreg[t][e];
+    }
   }
 
   // Spectra m0 .. m0+ng-1 of the tile; niter >= ng is the same for every
@@ -490,6 +514,8 @@ struct FusedEngine {
 #pragma unroll
         for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
         v2f v[B][R];
+        uint32_t hb = hl;
+        if constexpr (CL) asm volatile("" : "+v"(hb));
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
@@ -498,12 +524,14 @@ struct FusedEngine {
               v[b][e] = ring[(k + b) % Q][e];
             } else {
               v2f acc;
-              acc.x = hreg[0][e] * ring[(k + b) % Q][e].x;
-              acc.y = hreg[0][e] * ring[(k + b) % Q][e].y;
+              const float h0 = hcoef(hb, 0, e);
+              acc.x = h0 * ring[(k + b) % Q][e].x;
+              acc.y = h0 * ring[(k + b) % Q][e].y;
 #pragma unroll
               for (int t = 1; t < TP; ++t) {
-                acc.x = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].x, acc.x);
-                acc.y = fmaf(hreg[t][e], ring[(k + b + t) % Q][e].y, acc.y);
+                const float ht = hcoef(hb, t, e);
+                acc.x = fmaf(ht, ring[(k + b + t) % Q][e].x, acc.x);
+                acc.y = fmaf(ht, ring[(k + b + t) % Q][e].y, acc.y);
               }
               v[b][e] = acc;
             }
@@ -679,7 +707,7 @@ static const KernelInfo& fused_info() {
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
   static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>,
-                             (N / R) * G, G, Fft::lds_bytes()};
+                             (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>::lds_bytes()};
   return ki;
 }
 

@@ -358,10 +358,10 @@ static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, con
                                     const float* coef, int T, hipStream_t st) {
   constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
+  using Eng = FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   static const int occ = [&] {
-    KernelInfo ki{(const void*)kern, (N / R) * G, G, Fft::lds_bytes()};
+    KernelInfo ki{(const void*)kern, (N / R) * G, G, Eng::lds_bytes()};
     return occupancy(ki);
   }();
   if (!cls) return hipSuccess;                 // warm-up call: occupancy only
@@ -369,7 +369,7 @@ static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, con
   const long long need = (max_tiles + G - 1) / G;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((N / R) * G), Fft::lds_bytes(), st, cls, tiles, coef,
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((N / R) * G), Eng::lds_bytes(), st, cls, tiles, coef,
                      (const v2f*)pd.tw, TP - T);
   return hipGetLastError();
 }
