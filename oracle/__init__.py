@@ -5,3 +5,4 @@ this package; the product path never does.
 """
 from .ppf_oracle import (as_complex128, dft, dft_matrix_columns, fir_presum,  # noqa: F401
                          n_spectra, ppf, ppf_power, ppf_stream, twiddles)
+from . import design  # noqa: F401,E402  (prototype-filter design)
