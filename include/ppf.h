@@ -70,6 +70,15 @@ enum ppf_fft_mode {
     PPF_FFT_MFMA_F16 = 1  /* radix-16 stages as FP16 MFMA, FP32 accumulate */
 };
 
+/* Windows of the prototype-filter designer (ppf_design_coeffs). */
+enum ppf_window {
+    PPF_WIN_RECT = 0,     /* 1 */
+    PPF_WIN_HAMMING = 1,  /* 0.54 - 0.46 cos(2 pi j/(L-1)) */
+    PPF_WIN_HANN = 2,     /* 0.5 - 0.5 cos(2 pi j/(L-1)) */
+    PPF_WIN_KAISER = 3,   /* I0(beta sqrt(1 - r^2)) / I0(beta), r = 2j/(L-1) - 1 */
+    PPF_WIN_USER = 4      /* L values given by the caller */
+};
+
 /* Execution paths a plan can use (ppf_plan_set_path / ppf_plan_query). */
 enum ppf_path {
     PPF_PATH_AUTO = 0,     /* library's choice */
@@ -193,6 +202,41 @@ int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long lo
 
 /* ppf_destroy - wait for the plan's stream, then free the plan. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);
+
+/*
+ * ppf_design_coeffs - prototype coefficients for ppf_plan from the constant
+ * response function of section 2: the ideal pass band of one channel is a
+ * sinc in time, sampled over L = taps * n_channels points and tapered by a
+ * window (the paper uses the Kaiser window, with its parameter unstated):
+ *
+ *     v[j] = w[j] * sinc((j - (L-1)/2) / n_channels),  sinc(u) = sin(pi u)/(pi u)
+ *     coeffs[j] = v[j] / sum_i v[i]                    (gain 1 at DC)
+ *
+ * so the pass band reaches half amplitude half a bin from the channel
+ * centre. w is the window (enum ppf_window) over j = 0 .. L-1; L = 1 gives
+ * w = 1. Computed on the current HIP device in FP64 and rounded once to
+ * FP32; synchronous (plan time: it allocates and frees device memory).
+ *
+ * beta:        Kaiser parameter, 0 <= beta <= 60 (PPF_WIN_KAISER only;
+ *              ppf_kaiser_beta gives it from a stop-band attenuation).
+ * user_window: host pointer, L doubles (PPF_WIN_USER only, else ignored).
+ * coeffs:      host pointer, L floats; the caller owns it.
+ * n_channels >= 1 and taps >= 1 (any values, not only the sizes a plan
+ * supports), else PPF_ERR_INVALID; L above 2^20 is PPF_ERR_UNSUPPORTED.
+ * A bad window, beta out of range or not a number, a NULL coeffs, or a
+ * NULL user_window for PPF_WIN_USER is PPF_ERR_INVALID, as is a window
+ * whose windowed sinc sums to zero or to a value that is not finite.
+ */
+int ppf_design_coeffs(int n_channels, int taps, int window, double beta, const double* user_window,
+                      float* coeffs);
+
+/*
+ * ppf_kaiser_beta - Kaiser's empirical rule for the window parameter from
+ * the wanted stop-band attenuation A in dB: 0.1102 (A - 8.7) for A > 50,
+ * 0.5842 (A - 21)^0.4 + 0.07886 (A - 21) for 21 <= A <= 50, else 0.
+ * Host arithmetic only. A not a number or a NULL beta is PPF_ERR_INVALID.
+ */
+int ppf_kaiser_beta(double atten_db, double* beta);
 
 /* ------------------------------------------------------------------------
  * Stream form.

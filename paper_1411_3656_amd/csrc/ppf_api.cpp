@@ -588,6 +588,54 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
   }
 }
 
+int ppf_design_coeffs(int n_channels, int taps, int window, double beta, const double* user_window,
+                      float* coeffs) {
+  if (n_channels < 1 || taps < 1) return fail(PPF_ERR_INVALID, "n_channels and taps must be >= 1");
+  const long long L = (long long)n_channels * taps;
+  if (L > (1ll << 20)) return fail(PPF_ERR_UNSUPPORTED, "prototype of %lld points exceeds 2^20", L);
+  if (window < PPF_WIN_RECT || window > PPF_WIN_USER) return fail(PPF_ERR_INVALID, "unknown window %d", window);
+  if (window == PPF_WIN_KAISER && !(beta >= 0.0 && beta <= 60.0))
+    return fail(PPF_ERR_INVALID, "Kaiser beta must be in [0, 60]");
+  if (window == PPF_WIN_USER && user_window == nullptr) return fail(PPF_ERR_INVALID, "user window is NULL");
+  if (coeffs == nullptr) return fail(PPF_ERR_INVALID, "coeffs is NULL");
+
+  // one device buffer: v (L doubles), user window (L doubles), h (L floats), sum
+  const size_t vb = (size_t)L * sizeof(double);
+  const size_t bytes = 2 * vb + (size_t)L * sizeof(float) + sizeof(double);
+  char* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc (design)");
+  double* v = (double*)d;
+  double* user = (double*)(d + vb);
+  float* h = (float*)(d + 2 * vb);
+  double* sum = (double*)(d + 2 * vb + (size_t)L * sizeof(float));
+  double total = 0.0;
+  int st = PPF_OK;
+  if (window == PPF_WIN_USER && (e = hipMemcpy(user, user_window, vb, hipMemcpyHostToDevice)) != hipSuccess) {
+    st = fail_hip(e, "hipMemcpy (user window)");
+  } else if ((e = ppf::launch_design((int)L, n_channels, window, beta, user, v, h, sum, nullptr)) != hipSuccess) {
+    st = fail_hip(e, "design kernels");
+  } else if ((e = hipMemcpy(&total, sum, sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) {
+    st = fail_hip(e, "hipMemcpy (design sum)");
+  } else if (!std::isfinite(total) || total == 0.0) {
+    st = fail(PPF_ERR_INVALID, "the windowed sinc sums to %g", total);
+  } else if ((e = hipMemcpy(coeffs, h, (size_t)L * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess) {
+    st = fail_hip(e, "hipMemcpy (coefficients)");
+  }
+  const hipError_t ef = hipFree(d);
+  if (st == PPF_OK && ef != hipSuccess) st = fail_hip(ef, "hipFree (design)");
+  return st;
+}
+
+int ppf_kaiser_beta(double atten_db, double* beta) {
+  if (beta == nullptr || std::isnan(atten_db)) return fail(PPF_ERR_INVALID, "atten_db is NaN or beta is NULL");
+  const double a = atten_db;
+  if (a > 50.0) *beta = 0.1102 * (a - 8.7);
+  else if (a >= 21.0) *beta = 0.5842 * std::pow(a - 21.0, 0.4) + 0.07886 * (a - 21.0);
+  else *beta = 0.0;
+  return PPF_OK;
+}
+
 int ppf_destroy(ppf_plan_t plan) {
   if (!plan) return PPF_OK;
   if (plan->h2d) hipStreamSynchronize(plan->h2d);

@@ -112,6 +112,11 @@ bool mfma_available(int N, int TP);
 size_t mfma_coef_bytes();
 void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst);
 hipError_t launch_w256(void* table, hipStream_t st);
+
+// Prototype-filter design (plan time): v (L doubles) and h (L floats) and
+// sum (1 double) are device buffers; user holds L doubles for PPF_WIN_USER.
+hipError_t launch_design(int L, int N, int window, double beta, const double* user, double* v, float* h,
+                         double* sum, hipStream_t st);
 hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st);
 
 }  // namespace ppf

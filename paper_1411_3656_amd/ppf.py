@@ -35,6 +35,11 @@ PPF_PATH_AUTO, PPF_PATH_FUSED, PPF_PATH_TWO_PASS = 0, 1, 2
 (PPF_Q_N, PPF_Q_TAPS, PPF_Q_PATH, PPF_Q_WORKSPACE_BYTES, PPF_Q_IN_TYPE, PPF_Q_FFT_MODE,
  PPF_Q_COEFF_SHIFT, PPF_Q_FUSED_AVAILABLE) = range(8)
 
+# windows of the prototype-filter designer (enum ppf_window)
+PPF_WIN_RECT, PPF_WIN_HAMMING, PPF_WIN_HANN, PPF_WIN_KAISER, PPF_WIN_USER = range(5)
+WINDOWS = {"rect": PPF_WIN_RECT, "hamming": PPF_WIN_HAMMING, "hann": PPF_WIN_HANN, "kaiser": PPF_WIN_KAISER,
+           "user": PPF_WIN_USER}
+
 SAMPLE_BYTES = {PPF_C32: 8, PPF_C16: 4, PPF_CI8: 2}
 
 _c_ll = ctypes.c_longlong
@@ -71,6 +76,8 @@ _SIGNATURES = [
     ("ppf_execute_host", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_ll]),
     ("ppf_execute_power", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_int]),
     ("ppf_destroy", _c_int, [_c_vp]),
+    ("ppf_design_coeffs", _c_int, [_c_int, _c_int, _c_int, ctypes.c_double, _c_vp, _c_vp]),
+    ("ppf_kaiser_beta", _c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     ("ppf_stream_create", _c_vp, [_c_vp]),
     ("ppf_stream_push", _c_int, [_c_vp, _c_vp]),
     ("ppf_stream_get_history", _c_int, [_c_vp, _c_vp]),
@@ -100,6 +107,11 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not _LIB_PATH.exists():
             raise RuntimeError(f"{_LIB_PATH} is not built: run `python -m paper_1411_3656_amd.build`")
+        # torch ships its own HIP runtime. Loaded first, it is the runtime the
+        # library's HIP calls bind to as well; if the library loads the
+        # system runtime first, torch later finds no devices. torch provides
+        # the device memory and streams, so it goes first.
+        import torch  # noqa: F401
         handle = ctypes.CDLL(str(_LIB_PATH))
         for name, res, args in _SIGNATURES:
             fn = getattr(handle, name)
@@ -201,6 +213,26 @@ def ppf_execute_power(plan: int, inp, out_power, nspectra: int, k_int: int) -> i
 
 def ppf_destroy(plan: int) -> int:
     return _check(lib().ppf_destroy(plan))
+
+
+def ppf_design_coeffs(n_channels: int, taps: int, window, beta: float = 0.0, user_window=None):
+    """Prototype coefficients (host float32, taps*n_channels values) designed
+    on the GPU. window: a ppf_window value or one of WINDOWS' names."""
+    import numpy as np
+    w = WINDOWS[window] if isinstance(window, str) else int(window)
+    out = np.empty(max(0, int(n_channels) * int(taps)), dtype=np.float32)
+    user = None if user_window is None else np.ascontiguousarray(user_window, dtype=np.float64)
+    if user is not None and user.size != out.size:
+        raise ValueError("user_window must hold taps*n_channels values")
+    _check(lib().ppf_design_coeffs(int(n_channels), int(taps), w, float(beta), _addr(user),
+                                   _addr(out) if out.size else None))
+    return out
+
+
+def ppf_kaiser_beta(atten_db: float) -> float:
+    beta = ctypes.c_double()
+    _check(lib().ppf_kaiser_beta(float(atten_db), ctypes.byref(beta)))
+    return beta.value
 
 
 def ppf_stream_create(plan: int) -> int:
