@@ -81,7 +81,11 @@ bool fused_ok_for(int N, int TP, int in_type) {
 
 // Largest FIR workspace of the two-pass path, in bytes (stays inside the
 // 256 MB Infinity Cache between the FIR and the FFT launch of a chunk).
-constexpr size_t kWorkspaceBytes = 64ull << 20;
+// PPF_WORKSPACE_MIB overrides it at build time (tuning).
+#ifndef PPF_WORKSPACE_MIB
+#define PPF_WORKSPACE_MIB 128
+#endif
+constexpr size_t kWorkspaceBytes = (size_t)PPF_WORKSPACE_MIB << 20;
 
 }  // namespace
 

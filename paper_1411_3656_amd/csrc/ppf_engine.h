@@ -235,19 +235,37 @@ struct GroupFft {
     if constexpr (!TWG) load_stage_tw<1>();
   }
 
+  // twiddle sets of stage S: butterflies j + i*W share b % Ns when Ns <= W
   template <int S>
-  __device__ __forceinline__ v2f twiddle(int i, int q) const {
+  static constexpr int stage_sets() {
+    return ns_at(N, RX, S) <= W ? 1 : R / radix_at(N, RX, S);
+  }
+
+  // TWG: stage S's twiddles are read from the global table when the stage
+  // starts, all in one batch. The addresses are loop-invariant, so a
+  // hoisted load would keep every stage's twiddles live in registers; one
+  // opaque zero per stage ties the batch to its stage, and the loads are
+  // in flight together (one wait) while the stage reads its LDS inputs.
+  template <int S>
+  __device__ __forceinline__ void fetch_stage_tw(v2f* tl) const {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+#pragma unroll
+    for (int ib = 0; ib < stage_sets<S>(); ++ib) {
+      const int k = (j + ib * W) % Ns;
+#pragma unroll
+      for (int q = 1; q < r; ++q) tl[ib * (r - 1) + q - 1] = tw[k * q * (N / (Ns * r)) + z];
+    }
+  }
+
+  template <int S>
+  __device__ __forceinline__ v2f twiddle(const v2f* tl, int i, int q) const {
+    constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
+    const int ib = (Ns <= W) ? 0 : i;
     if constexpr (TWG) {
-      // read at the point of use: the address is loop-invariant, and a
-      // hoisted load would keep every stage's twiddles live in registers;
-      // an opaque zero ties the load to this stage
-      int z;
-      asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-      const int k = (j + i * W) % Ns;
-      return tw[k * q * (N / (Ns * r)) + z];
+      return tl[ib * (r - 1) + q - 1];
     } else {
-      const int ib = (Ns <= W) ? 0 : i;
       return twr[tw_offset(N, R, RX, S) + ib * (r - 1) + q - 1];
     }
   }
@@ -256,6 +274,8 @@ struct GroupFft {
   __device__ __forceinline__ void stage(v2f (&v)[B][R]) {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     constexpr int nb = R / r;
+    v2f tl[TWG && S > 0 ? stage_sets<S>() * (r - 1) : 1];
+    if constexpr (TWG && S > 0) fetch_stage_tw<S>(tl);
     if constexpr (S > 0) {
       const int buf = DB ? par : 0;
 #pragma unroll
@@ -274,7 +294,7 @@ struct GroupFft {
       for (int i = 0; i < nb; ++i)
 #pragma unroll
         for (int q = 1; q < r; ++q) {
-          const v2f w = twiddle<S>(i, q);
+          const v2f w = twiddle<S>(tl, i, q);
 #pragma unroll
           for (int b = 0; b < B; ++b) v[b][i + q * nb] = cmul(v[b][i + q * nb], w);
         }
@@ -653,7 +673,7 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
 #endif
 
 // elements per thread R and groups per block G for the FFT of N points
-constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : 16); }
+constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : (N >= 16384 ? 32 : 16)); }
 constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
 constexpr int cfg_W(int N) { return N / cfg_R(N); }
 constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
