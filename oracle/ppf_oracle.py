@@ -61,7 +61,7 @@ def as_complex128(x) -> np.ndarray:
     """
     a = np.asarray(x)
     if np.iscomplexobj(a):
-        return a.astype(np.complex128).reshape(-1)
+        return a.astype(np.complex128, copy=False).reshape(-1)
     if a.ndim == 2 and a.shape[1] == 2:
         re = a[:, 0].astype(np.float64)
         im = a[:, 1].astype(np.float64)
