@@ -205,6 +205,8 @@ def main() -> int:
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk-mib", type=int, default=0,
+                    help="mb: input MiB per pipeline chunk (0: the library's default)")
     ap.add_argument("--windows", type=int, default=0,
                     help="also report the mean step time of this many consecutive slices of the timed steps")
     args = ap.parse_args()
@@ -324,17 +326,19 @@ def main() -> int:
         del x
         out = torch.empty((m_total, n), dtype=torch.complex64).pin_memory()
         plan = ppf.Plan(n, taps, h32)
+        # spectra per pipeline chunk: 0 is the library's default (192 MiB of input)
+        chunk = (args.chunk_mib << 20) // (n * 8) if args.chunk_mib > 0 else 0
         stream = torch.cuda.current_stream()
         steps = min(args.steps, 20)
         warm = min(args.warmup, 2)
         for _ in range(warm):
-            plan.execute_host(xin, out)
+            plan.execute_host(xin, out, chunk_spectra=chunk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(steps):
-            plan.execute_host(xin, out)
+            plan.execute_host(xin, out, chunk_spectra=chunk)
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
@@ -343,11 +347,15 @@ def main() -> int:
         in_b = metrics.input_bytes(n, m_total)
         gbps = in_b / (ms * 1e-3) / 1e9
         pcie = (in_b + m_total * n * 8) / (ms * 1e-3) / 1e9
-        # the link's own rates with the same page-locked buffers: each
-        # direction alone, and both at once on two streams
+        # the link's own rates with the same page-locked buffers, copied in
+        # 128 MiB pieces as the pipeline does: each direction alone, and
+        # both at once on two streams
         dev_in = torch.empty(xin.shape, dtype=xin.dtype, device="cuda")
         dev_out = torch.empty(out.shape, dtype=out.dtype, device="cuda")
         s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+        piece = (128 << 20) // 8
+        flat_in, flat_dev_in = xin.reshape(-1), dev_in.reshape(-1)
+        flat_out, flat_dev_out = out.reshape(-1), dev_out.reshape(-1)
 
         def timed(fn, reps=3):
             torch.cuda.synchronize()
@@ -357,17 +365,24 @@ def main() -> int:
             torch.cuda.synchronize()
             return (time.perf_counter() - t) / reps
 
-        def h2d():
+        def h2d(i):
             with torch.cuda.stream(s_in):
-                dev_in.copy_(xin, non_blocking=True)
+                flat_dev_in[i:i + piece].copy_(flat_in[i:i + piece], non_blocking=True)
 
-        def d2h():
+        def d2h(i):
             with torch.cuda.stream(s_out):
-                out.copy_(dev_out, non_blocking=True)
+                flat_out[i:i + piece].copy_(flat_dev_out[i:i + piece], non_blocking=True)
 
-        t_h2d = timed(h2d)
-        t_d2h = timed(d2h)
-        t_both = timed(lambda: (h2d(), d2h()))
+        def both():
+            for i in range(0, max(flat_in.numel(), flat_out.numel()), piece):
+                if i < flat_in.numel():
+                    h2d(i)
+                if i < flat_out.numel():
+                    d2h(i)
+
+        t_h2d = timed(lambda: [h2d(i) for i in range(0, flat_in.numel(), piece)])
+        t_d2h = timed(lambda: [d2h(i) for i in range(0, flat_out.numel(), piece)])
+        t_both = timed(both)
         link = {"h2d_gbps": round(in_b / t_h2d / 1e9, 2), "d2h_gbps": round(out.numel() * 8 / t_d2h / 1e9, 2),
                 "both_directions_gbps": round((in_b + out.numel() * 8) / t_both / 1e9, 2)}
         del dev_in, dev_out
@@ -380,7 +395,8 @@ def main() -> int:
             "pcie_copy_only": link,
             "pcie_frac_of_copy_only": round(pcie / link["both_directions_gbps"], 3),
             "config": {"workload": "single_mode_host_resident_n1024_t8_2p27", "N": n, "taps": taps,
-                       "nspectra": m_total, "host_memory": "page-locked", "chunk_input_bytes": 32 << 20},
+                       "nspectra": m_total, "host_memory": "page-locked",
+                       "chunk_input_bytes": (chunk * n * 8) if chunk else 192 << 20},
             "paper_context_mb": PAPER_MB}), flush=True)
         return 0
 

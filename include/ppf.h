@@ -168,17 +168,18 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
  * host_in:  host pointer, (nspectra + T - 1) * N samples of the plan's
  *           input type.
  * host_out: host pointer, nspectra * N complex FP32 spectra.
- * chunk_spectra: spectra per pipeline chunk (0 selects about 32 MiB of
+ * chunk_spectra: spectra per pipeline chunk (0 selects about 192 MiB of
  *           input per chunk).
  *
  * The batch is cut into chunks of consecutive spectra; chunk i's input
  * (its spectra plus the T-1 blocks that follow) is copied to a device
- * staging buffer on a copy stream while chunk i-1 is transformed on the
- * plan's stream and chunk i-2's spectra are copied back on another copy
- * stream. The plan's stream completes when every spectrum is in host_out.
- * Host buffers must stay valid until then and should be page-locked
- * (hipHostMalloc) for the copies to run asynchronously at full rate.
- * The plan owns two pairs of staging buffers, allocated on first use.
+ * staging buffer on a copy stream while earlier chunks are transformed on
+ * the plan's stream and copied back on another copy stream. The plan owns
+ * three pairs of staging buffers (allocated on first use, grown to the
+ * chunk size), so up to three chunks are in flight. The plan's stream
+ * completes when every spectrum is in host_out. Host buffers must stay
+ * valid until then and should be page-locked (hipHostMalloc) for the
+ * copies to run asynchronously at full rate.
  * Errors as ppf_execute, plus PPF_ERR_NOMEM for the staging buffers.
  * Not thread-safe against other calls on the same plan.
  */

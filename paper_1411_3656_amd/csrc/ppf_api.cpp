@@ -87,6 +87,16 @@ bool fused_ok_for(int N, int TP, int in_type) {
 #endif
 constexpr size_t kWorkspaceBytes = (size_t)PPF_WORKSPACE_MIB << 20;
 
+// Single mode: staging pairs in the copy-in / transform / copy-out pipeline
+// and the default input bytes per chunk (build-time tuning).
+#ifndef PPF_HOST_STAGES
+#define PPF_HOST_STAGES 3
+#endif
+#ifndef PPF_HOST_CHUNK_MIB
+#define PPF_HOST_CHUNK_MIB 192
+#endif
+constexpr int kHostStages = PPF_HOST_STAGES;
+
 }  // namespace
 
 struct ppf_plan_s {
@@ -102,11 +112,11 @@ struct ppf_plan_s {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   // single mode (host-resident data): staging buffers, copy streams, events
-  void* h_in[2] = {nullptr, nullptr};
-  void* h_out[2] = {nullptr, nullptr};
+  void* h_in[kHostStages] = {};
+  void* h_out[kHostStages] = {};
   size_t h_in_cap = 0, h_out_cap = 0;
   hipStream_t h2d = nullptr, d2h = nullptr;
-  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
+  hipEvent_t ev_in[kHostStages] = {}, ev_comp[kHostStages] = {}, ev_out[kHostStages] = {};
   hipEvent_t ev_start = nullptr;
   long long chunk_spectra = 0;
   hipStream_t stream = nullptr;
@@ -137,7 +147,7 @@ struct ppf_plan_s {
     if (d_ones) hipFree(d_ones);
     if (d_tw) hipFree(d_tw);
     if (d_ws) hipFree(d_ws);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kHostStages; ++i) {
       if (h_in[i]) hipFree(h_in[i]);
       if (h_out[i]) hipFree(h_out[i]);
       if (ev_in[i]) hipEventDestroy(ev_in[i]);
@@ -264,7 +274,7 @@ int ensure_host_pipe(ppf_plan_t p, long long chunk) {
   if (!p->h2d) {
     e = hipStreamCreateWithFlags(&p->h2d, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->d2h, hipStreamNonBlocking);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < kHostStages && e == hipSuccess; ++i) {
       e = hipEventCreateWithFlags(&p->ev_in[i], hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_comp[i], hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_out[i], hipEventDisableTiming);
@@ -278,18 +288,18 @@ int ensure_host_pipe(ppf_plan_t p, long long chunk) {
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return fail_hip(e, "single-mode synchronize");
     }
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kHostStages; ++i) {
       if (p->h_in[i]) hipFree(p->h_in[i]);
       if (p->h_out[i]) hipFree(p->h_out[i]);
       p->h_in[i] = p->h_out[i] = nullptr;
     }
     p->h_in_cap = p->h_out_cap = 0;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < kHostStages && e == hipSuccess; ++i) {
       e = hipMalloc(&p->h_in[i], in_need);
       if (e == hipSuccess) e = hipMalloc(&p->h_out[i], out_need);
     }
     if (e != hipSuccess) {
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < kHostStages; ++i) {
         if (p->h_in[i]) hipFree(p->h_in[i]);
         if (p->h_out[i]) hipFree(p->h_out[i]);
         p->h_in[i] = p->h_out[i] = nullptr;
@@ -549,7 +559,7 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
     const size_t out_bytes = (size_t)nspectra * N * 8;
     if (overlaps((uintptr_t)host_in, in_bytes, (uintptr_t)host_out, out_bytes))
       return fail(PPF_ERR_INVALID, "host_in and host_out overlap");
-    long long chunk = chunk_spectra > 0 ? chunk_spectra : (long long)((32ull << 20) / ((size_t)N * sb));
+    long long chunk = chunk_spectra > 0 ? chunk_spectra : (long long)(((size_t)PPF_HOST_CHUNK_MIB << 20) / ((size_t)N * sb));
     if (chunk < 1) chunk = 1;
     if (chunk > nspectra) chunk = nspectra;
     int st = ensure_host_pipe(plan, chunk);
@@ -560,18 +570,19 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->d2h, plan->ev_start, 0);
     const long long nch = (nspectra + chunk - 1) / chunk;
     for (long long i = 0; i < nch && e == hipSuccess; ++i) {
-      const int b = (int)(i & 1);
+      const int b = (int)(i % kHostStages);
       const long long m0 = i * chunk;
       const long long k = nspectra - m0 < chunk ? nspectra - m0 : chunk;
       const size_t kin = (size_t)(k + plan->T - 1) * N * sb;
-      // buffer b is free once chunk i-2 was transformed (input) and copied back (output)
-      if (i >= 2) e = hipStreamWaitEvent(plan->h2d, plan->ev_comp[b], 0);
+      // buffer b is free once chunk i-kHostStages was transformed (input)
+      // and copied back (output)
+      if (i >= kHostStages) e = hipStreamWaitEvent(plan->h2d, plan->ev_comp[b], 0);
       if (e == hipSuccess)
         e = hipMemcpyAsync(plan->h_in[b], (const char*)host_in + (size_t)m0 * N * sb, kin, hipMemcpyHostToDevice,
                            plan->h2d);
       if (e == hipSuccess) e = hipEventRecord(plan->ev_in[b], plan->h2d);
       if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in[b], 0);
-      if (e == hipSuccess && i >= 2) e = hipStreamWaitEvent(plan->stream, plan->ev_out[b], 0);
+      if (e == hipSuccess && i >= kHostStages) e = hipStreamWaitEvent(plan->stream, plan->ev_out[b], 0);
       if (e != hipSuccess) break;
       st = run_batch(plan, plan->h_in[b], 0, plan->h_in[b], plan->h_out[b], k);
       if (st != PPF_OK) return st;
@@ -583,7 +594,7 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
       if (e == hipSuccess) e = hipEventRecord(plan->ev_out[b], plan->d2h);
     }
     // the plan's stream completes after the last copy back
-    if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_out[(nch - 1) & 1], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_out[(nch - 1) % kHostStages], 0);
     if (e != hipSuccess) return fail_hip(e, "single-mode pipeline");
     g_status = PPF_OK;
     return PPF_OK;
