@@ -143,22 +143,22 @@ struct ppf_plan_s {
     return m;
   }
   ~ppf_plan_s() {
-    if (d_coef) hipFree(d_coef);
-    if (d_ones) hipFree(d_ones);
-    if (d_tw) hipFree(d_tw);
-    if (d_ws) hipFree(d_ws);
+    if (d_coef) (void)hipFree(d_coef);
+    if (d_ones) (void)hipFree(d_ones);
+    if (d_tw) (void)hipFree(d_tw);
+    if (d_ws) (void)hipFree(d_ws);
     for (int i = 0; i < kHostStages; ++i) {
-      if (h_in[i]) hipFree(h_in[i]);
-      if (h_out[i]) hipFree(h_out[i]);
-      if (ev_in[i]) hipEventDestroy(ev_in[i]);
-      if (ev_comp[i]) hipEventDestroy(ev_comp[i]);
-      if (ev_out[i]) hipEventDestroy(ev_out[i]);
+      if (h_in[i]) (void)hipFree(h_in[i]);
+      if (h_out[i]) (void)hipFree(h_out[i]);
+      if (ev_in[i]) (void)hipEventDestroy(ev_in[i]);
+      if (ev_comp[i]) (void)hipEventDestroy(ev_comp[i]);
+      if (ev_out[i]) (void)hipEventDestroy(ev_out[i]);
     }
-    if (ev_start) hipEventDestroy(ev_start);
-    if (h2d) hipStreamDestroy(h2d);
-    if (d2h) hipStreamDestroy(d2h);
-    if (d_coef16) hipFree(d_coef16);
-    if (d_w256) hipFree(d_w256);
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    if (h2d) (void)hipStreamDestroy(h2d);
+    if (d2h) (void)hipStreamDestroy(d2h);
+    if (d_coef16) (void)hipFree(d_coef16);
+    if (d_w256) (void)hipFree(d_w256);
   }
 };
 
@@ -169,8 +169,8 @@ struct ppf_stream_s {
   long long hist_samples = 0;
   long long pushed_spectra = 0;
   ~ppf_stream_s() {
-    if (hist[0]) hipFree(hist[0]);
-    if (hist[1]) hipFree(hist[1]);
+    if (hist[0]) (void)hipFree(hist[0]);
+    if (hist[1]) (void)hipFree(hist[1]);
   }
 };
 
@@ -181,7 +181,7 @@ int ensure_workspace(ppf_plan_t p, long long min_spectra = 1) {
   if (p->d_ws) {   // grow: earlier work on the plan's stream may still read it
     const hipError_t es = hipStreamSynchronize(p->stream);
     if (es != hipSuccess) return fail_hip(es, "workspace synchronize");
-    hipFree(p->d_ws);
+    (void)hipFree(p->d_ws);
     p->d_ws = nullptr;
   }
   long long k = (long long)(kWorkspaceBytes / (8ull * p->N));
@@ -289,8 +289,8 @@ int ensure_host_pipe(ppf_plan_t p, long long chunk) {
       if (e != hipSuccess) return fail_hip(e, "single-mode synchronize");
     }
     for (int i = 0; i < kHostStages; ++i) {
-      if (p->h_in[i]) hipFree(p->h_in[i]);
-      if (p->h_out[i]) hipFree(p->h_out[i]);
+      if (p->h_in[i]) (void)hipFree(p->h_in[i]);
+      if (p->h_out[i]) (void)hipFree(p->h_out[i]);
       p->h_in[i] = p->h_out[i] = nullptr;
     }
     p->h_in_cap = p->h_out_cap = 0;
@@ -300,8 +300,8 @@ int ensure_host_pipe(ppf_plan_t p, long long chunk) {
     }
     if (e != hipSuccess) {
       for (int i = 0; i < kHostStages; ++i) {
-        if (p->h_in[i]) hipFree(p->h_in[i]);
-        if (p->h_out[i]) hipFree(p->h_out[i]);
+        if (p->h_in[i]) (void)hipFree(p->h_in[i]);
+        if (p->h_out[i]) (void)hipFree(p->h_out[i]);
         p->h_in[i] = p->h_out[i] = nullptr;
       }
       return fail_hip(e, "single-mode staging buffers");
@@ -653,8 +653,8 @@ int ppf_kaiser_beta(double atten_db, double* beta) {
 
 int ppf_destroy(ppf_plan_t plan) {
   if (!plan) return PPF_OK;
-  if (plan->h2d) hipStreamSynchronize(plan->h2d);
-  if (plan->d2h) hipStreamSynchronize(plan->d2h);
+  if (plan->h2d) (void)hipStreamSynchronize(plan->h2d);
+  if (plan->d2h) (void)hipStreamSynchronize(plan->d2h);
   hipError_t e = hipStreamSynchronize(plan->stream);
   delete plan;
   if (e != hipSuccess) return fail_hip(e, "ppf_destroy synchronize");

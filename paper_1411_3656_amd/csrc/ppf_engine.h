@@ -716,7 +716,7 @@ static int device_cus() {
 
 static int occupancy(const KernelInfo& ki) {
   int occ = 0;
-  if (ki.lds > 64 * 1024) hipFuncSetAttribute(ki.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ki.lds);
+  if (ki.lds > 64 * 1024) (void)hipFuncSetAttribute(ki.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ki.lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ki.fn, ki.block, ki.lds) != hipSuccess || occ <= 0) occ = 1;
   return occ;
 }
@@ -725,7 +725,6 @@ template <int N, int TP, bool UNIT, bool POW = false>
 static const KernelInfo& fused_info() {
   constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
   constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
   static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>,
                              (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>::lds_bytes()};
   return ki;

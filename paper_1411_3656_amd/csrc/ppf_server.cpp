@@ -208,7 +208,7 @@ int class_of(ppf_server_s* s, ppf_plan_t plan) {
 // Capture the slot's graph for the current class set (scheduler thread, slot idle).
 int build_graph(ppf_server_s* s, Slot& sl) {
   if (sl.exec) {
-    hipGraphExecDestroy(sl.exec);
+    (void)hipGraphExecDestroy(sl.exec);
     sl.exec = nullptr;
   }
   for (const ClassInfo& ci : s->classes) {
@@ -245,11 +245,11 @@ int build_graph(ppf_server_s* s, Slot& sl) {
   }
   hipError_t e2 = hipStreamEndCapture(s->launch, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return sfail_hip(e != hipSuccess ? e : e2, "graph capture");
   }
   e = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     sl.exec = nullptr;
     return sfail_hip(e, "graph instantiate");
@@ -555,8 +555,8 @@ void scheduler(ppf_server_s* s) {
         SrvStream& st = *it->second;
         if (st.closing && st.outstanding == 0 && st.queue.empty()) {
           if (st.admitted) s->used -= st.state_bytes;
-          if (st.hist[0]) hipFree(st.hist[0]);
-          if (st.hist[1]) hipFree(st.hist[1]);
+          if (st.hist[0]) (void)hipFree(st.hist[0]);
+          if (st.hist[1]) (void)hipFree(st.hist[1]);
           it = s->streams.erase(it);
           progressed = true;
         } else {
@@ -636,29 +636,29 @@ void scheduler(ppf_server_s* s) {
 void destroy_server(ppf_server_s* s) {
   for (int k = 0; k < kMaxSlots; ++k) {
     Slot& sl = s->slots[k];
-    if (sl.exec) hipGraphExecDestroy(sl.exec);
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
     if (sl.stream) {
-      hipStreamSynchronize(sl.stream);
-      hipStreamDestroy(sl.stream);
+      (void)hipStreamSynchronize(sl.stream);
+      (void)hipStreamDestroy(sl.stream);
     }
-    if (sl.done) hipEventDestroy(sl.done);
-    if (sl.start) hipEventDestroy(sl.start);
-    if (sl.host) hipHostFree(sl.host);
-    if (sl.dev) hipFree(sl.dev);
-    if (sl.ws) hipFree(sl.ws);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.start) (void)hipEventDestroy(sl.start);
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    if (sl.ws) (void)hipFree(sl.ws);
   }
   for (auto& kv : s->streams) {
-    if (kv.second->hist[0]) hipFree(kv.second->hist[0]);
-    if (kv.second->hist[1]) hipFree(kv.second->hist[1]);
+    if (kv.second->hist[0]) (void)hipFree(kv.second->hist[0]);
+    if (kv.second->hist[1]) (void)hipFree(kv.second->hist[1]);
   }
   for (int c = 0; c < kMaxClasses; ++c) {
-    if (s->branch[c]) hipStreamDestroy(s->branch[c]);
-    if (s->join[c]) hipEventDestroy(s->join[c]);
+    if (s->branch[c]) (void)hipStreamDestroy(s->branch[c]);
+    if (s->join[c]) (void)hipEventDestroy(s->join[c]);
   }
-  if (s->hist_branch) hipStreamDestroy(s->hist_branch);
-  if (s->hist_join) hipEventDestroy(s->hist_join);
-  if (s->fork) hipEventDestroy(s->fork);
-  if (s->launch) hipStreamDestroy(s->launch);
+  if (s->hist_branch) (void)hipStreamDestroy(s->hist_branch);
+  if (s->hist_join) (void)hipEventDestroy(s->hist_join);
+  if (s->fork) (void)hipEventDestroy(s->fork);
+  if (s->launch) (void)hipStreamDestroy(s->launch);
   delete s;
 }
 
@@ -875,8 +875,8 @@ int ppf_server_destroy(ppf_server_t s) {
   if (s->worker.joinable()) s->worker.join();
   const int err = s->async_error;
   for (int k = 0; k < s->nslots; ++k)
-    if (s->slots[k].stream) hipStreamSynchronize(s->slots[k].stream);
-  hipStreamSynchronize(s->launch);
+    if (s->slots[k].stream) (void)hipStreamSynchronize(s->slots[k].stream);
+  (void)hipStreamSynchronize(s->launch);
   destroy_server(s);
   return err == PPF_OK ? PPF_OK : sfail(err, "server had failed");
 }
