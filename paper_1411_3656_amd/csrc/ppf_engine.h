@@ -730,6 +730,12 @@ static const KernelInfo& fused_info() {
   return ki;
 }
 
+// Shortest tile of a batch launch, in units of the tap count (build-time
+// tuning): a tile of S spectra reads S + TP - 1 input blocks.
+#ifndef PPF_MIN_TILE
+#define PPF_MIN_TILE 1
+#endif
+
 // Largest number of spectra in one launch: block and spectrum indices stay
 // below 2^31 inside the kernels.
 constexpr long long kMaxLaunchSpectra = 1ll << 28;
@@ -760,7 +766,7 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   static const int occ = occupancy(ki);
   const long long resident_groups = (long long)device_cus() * occ * ki.G;
   long long S = (a.M + resident_groups - 1) / resident_groups;
-  if (S < 2 * TP) S = 2 * TP;                                  // bound the tap-window re-reads
+  if (S < PPF_MIN_TILE * TP) S = PPF_MIN_TILE * TP;            // bound the tap-window re-reads
   if (POW) S = (S + K - 1) / K * K;
   const long long groups = (a.M + S - 1) / S;
   const long long nblocks = (groups + ki.G - 1) / ki.G;
