@@ -368,6 +368,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 
 // Input blocks are streamed with non-temporal loads unless disabled at
 // build time (measured faster on MI355X for the one-pass batch).
+// 16-tap kernels for N <= 256: prefetch 2 and two waves per SIMD (tuning).
+#ifndef PPF_SMALL16
+#define PPF_SMALL16 1
+#endif
+
 #ifndef PPF_NT_LOADS
 #define PPF_NT_LOADS 1
 #endif
@@ -601,7 +606,7 @@ struct FusedEngine {
 // Batch form: a wave of tiles of S consecutive spectra covers the batch;
 // group g of block lb owns the tile (lb*G + g).
 template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false>
-__global__ void __launch_bounds__((N / R) * G)
+__global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_eu(PPF_SMALL16 && TP >= 16 && N <= 256 ? 2 : 1)))
 ppf_fused_kernel(FusedParams p) {
   constexpr int W = N / R;
   extern __shared__ float smem[];
@@ -628,7 +633,7 @@ ppf_fused_kernel(FusedParams p) {
 // block exits at the same tile index, after the same number of barriers.
 
 template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
-__global__ void __launch_bounds__((N / R) * G)
+__global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_eu(PPF_SMALL16 && TP >= 16 && N <= 256 ? 2 : 1)))
 ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, const v2f* tw, int d) {
   constexpr int W = N / R;
   extern __shared__ float smem[];
@@ -679,7 +684,8 @@ constexpr int cfg_W(int N) { return N / cfg_R(N); }
 constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
 constexpr int cfg_PF(int N, int TP) {
   return TP == 1 ? (N >= 16384 ? 0 : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
-                 : (N >= 2048 ? 2 : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
+                 : (N >= 2048 || (PPF_SMALL16 && TP >= 16 && N <= 256) ? 2
+                                  : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
 }
 constexpr bool cfg_TWG(int N) { return N >= 16384; }
 // spectra per FFT pass (build-time tuning; 4 measured best at N=1024, T=8)
