@@ -324,7 +324,8 @@ long long ppf_clock_ns(void);
 /* ppf_server_create - server with a device-memory budget in bytes for its own
  * buffers plus stream state, and 1..4 batches in flight. Starts the
  * scheduler thread. PPF_ERR_BUDGET if the budget cannot hold the server's
- * own buffers (max_inflight * ~64 MiB). Returns NULL on error. */
+ * own buffers: per in-flight batch, a 512 MiB two-pass workspace and its
+ * descriptor tables. Returns NULL on error. */
 ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight);
 
 /* ppf_server_open_stream - open a stream on a complex-FP32 plan (at most 8
