@@ -233,3 +233,66 @@ def test_runs_of_short_chunks_match_oracle():
         ppf.ppf_server_destroy(srv)
     for p, _ in plans.values():
         p.close()
+
+
+def test_c5_mix_sampled_streams():
+    """The serving workload's shape: 64 streams whose N in {256, 1024, 4096}
+    and T in {8, 16} are drawn from each stream's seed, sinc x Hamming
+    prototypes, chunks of 1..64 spectra submitted interleaved at random.
+    Every chunk of 8 sampled streams is checked against the oracle's stream
+    form; every output of the other streams must be finite."""
+    torch = _torch()
+    n_streams, chunks_per_stream = 64, 8
+    streams = []
+    for i in range(n_streams):
+        rng = np.random.default_rng(signals.SEED_BASE + 4 + 1000 * i)
+        n = int(rng.choice([256, 1024, 4096]))
+        taps = int(rng.choice([8, 16]))
+        lens = [int(v) for v in rng.integers(1, 65, chunks_per_stream)]
+        x = signals.complex_gaussian(sum(lens) * n, 1.0, seed=signals.SEED_BASE + 4 + 1000 * i + 1)
+        chunks, at = [], 0
+        for s in lens:
+            chunks.append(x[at * n:(at + s) * n])
+            at += s
+        streams.append(dict(n=n, taps=taps, lens=lens, chunks=chunks,
+                            dev_in=[torch.from_numpy(c).cuda() for c in chunks]))
+    shapes = sorted({(s["n"], s["taps"]) for s in streams})
+    coeffs = {key: signals.design_coeffs(key[0], key[1], "hamming").astype(np.float32) for key in shapes}
+    plans = _plans(coeffs)
+    print(f"case C5 mix: {n_streams} streams, classes {shapes}", flush=True)
+    srv = ppf.ppf_server_create(8 << 30, 2)
+    try:
+        ids, outs = {}, {}
+        for k, st in enumerate(streams):
+            ids[k] = ppf.ppf_server_open_stream(srv, plans[(st["n"], st["taps"])].handle)
+            outs[k] = [torch.full((s, st["n"]), float("nan"), dtype=torch.complex64, device="cuda")
+                       for s in st["lens"]]
+        cursor = [0] * n_streams
+        rng = np.random.default_rng(17)
+        live = list(range(n_streams))
+        while live:
+            k = live[int(rng.integers(len(live)))]
+            i = cursor[k]
+            st = streams[k]
+            ppf.ppf_server_submit(srv, ids[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=k * 1000 + i)
+            cursor[k] += 1
+            if cursor[k] == chunks_per_stream:
+                live.remove(k)
+        ppf.ppf_server_drain(srv, 120.0)
+        for k in range(n_streams):
+            ppf.ppf_server_close_stream(srv, ids[k])
+        torch.cuda.synchronize()
+    finally:
+        ppf.ppf_server_destroy(srv)
+        for p in plans.values():
+            p.close()
+    sampled = list(range(0, n_streams, n_streams // 8))
+    for k, st in enumerate(streams):
+        got = np.concatenate([o.cpu().numpy() for o in outs[k]])
+        assert np.isfinite(got).all(), k
+        if k in sampled:
+            ref = np.concatenate(oracle.ppf_stream(st["chunks"], coeffs[(st["n"], st["taps"])], st["n"], st["taps"]))
+            err = rel_err(got, ref)
+            print(f"C5 stream {k} N={st['n']} T={st['taps']} chunks {st['lens']}: max err / rms = {err:.3e}",
+                  flush=True)
+            assert err <= TOL, (k, err)
