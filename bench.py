@@ -205,6 +205,8 @@ def main() -> int:
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--point", default="",
+                    help="sweep: run only the point 'N,T' (e.g. 512,8)")
     ap.add_argument("--chunk-mib", type=int, default=0,
                     help="mb: input MiB per pipeline chunk (0: the library's default)")
     ap.add_argument("--windows", type=int, default=0,
@@ -422,11 +424,16 @@ def main() -> int:
         return 0
 
     if args.workload == "sweep":
+        only = tuple(int(v) for v in args.point.split(",")) if args.point else None
         for i, n in enumerate(SWEEP_N):
+            if only and n != only[0]:
+                continue
             x = signals.complex_gaussian(1 << 28, 1.0, seed=signals.SEED_BASE + 2 + 100 * i)
             x_dev = torch.from_numpy(x).cuda()
             del x
             for taps in SWEEP_T:
+                if only and taps != only[1]:
+                    continue
                 h32 = signals.design_coeffs(n, taps, "hann").astype(np.float32)
                 m_total = (1 << 28) // n - taps + 1
                 ms, used = run_point(torch, n, taps, m_total, x_dev, h32, args.steps, args.warmup, path)
