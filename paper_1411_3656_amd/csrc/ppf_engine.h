@@ -157,6 +157,18 @@ constexpr int tw_offset(int N, int R, int RX, int s) {
   return o;
 }
 constexpr int tw_total(int N, int R, int RX) { return tw_offset(N, R, RX, num_stages(N, RX)); }
+// Table-twiddle mode (TWG) with TWR: stages whose butterflies share one set
+// (Ns <= W) keep it in registers; the others read theirs from the table per
+// stage.
+constexpr int tw_count_twg(int N, int R, int RX, int s) {
+  if (s == 0) return 0;
+  return ns_at(N, RX, s) <= N / R ? radix_at(N, RX, s) - 1 : 0;
+}
+constexpr int tw_offset_twg(int N, int R, int RX, int s) {
+  int o = 0;
+  for (int i = 0; i < s; ++i) o += tw_count_twg(N, R, RX, i);
+  return o;
+}
 
 // LDS word address of element i of a plane. gfx950 LDS has 64 four-byte
 // banks serving a whole wave per access. For N >= 256 (one group per wave)
@@ -192,13 +204,19 @@ constexpr int plane_floats(int N, int W) {
 
 // B spectra go through the stages together: they share every barrier and
 // twiddle, and give each wave independent work between barriers.
-template <int N, int R, int RX, int G, int B, bool DB, bool TWG>
+template <int N, int R, int RX, int G, int B, bool DB, bool TWG, bool TWR = false>
 struct GroupFft {
   static constexpr int W = N / R;
   static constexpr int L = num_stages(N, RX);
   static constexpr int PL = plane_floats(N, W);      // floats per plane
   static constexpr int NBUF = DB ? 2 : 1;
-  static constexpr int NTW = TWG ? 1 : (tw_total(N, R, RX) > 0 ? tw_total(N, R, RX) : 1);
+  // TWR (with TWG): stages with one shared set keep it in registers
+  static constexpr int NTW_ = TWG ? (TWR ? tw_offset_twg(N, R, RX, L) : 0) : tw_total(N, R, RX);
+  static constexpr int NTW = NTW_ > 0 ? NTW_ : 1;
+  // offset of stage S's register twiddles
+  static constexpr int tw_off(int S) { return TWG ? tw_offset_twg(N, R, RX, S) : tw_offset(N, R, RX, S); }
+  // stage S reads its twiddles from the table when it starts
+  static constexpr bool tw_fetched(int S) { return TWG && S > 0 && (!TWR || ns_at(N, RX, S) > W); }
   static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
 
   float* lds;      // shared memory base of the block
@@ -214,10 +232,10 @@ struct GroupFft {
   template <int S>
   __device__ __forceinline__ void load_stage_tw() {
     if constexpr (S < L) {
-      if constexpr (S > 0) {
+      if constexpr (S > 0 && !tw_fetched(S)) {
         constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
         constexpr int nset = (Ns <= W) ? 1 : R / r;
-        constexpr int off = tw_offset(N, R, RX, S);
+        constexpr int off = tw_off(S);
         constexpr int step = N / (Ns * r);
 #pragma unroll
         for (int ib = 0; ib < nset; ++ib) {
@@ -232,7 +250,7 @@ struct GroupFft {
 
   __device__ __forceinline__ void init(float* smem, int grp_, int j_, const v2f* tw_) {
     lds = smem; grp = grp_; j = j_; par = 0; tw = tw_;
-    if constexpr (!TWG) load_stage_tw<1>();
+    load_stage_tw<1>();
   }
 
   // twiddle sets of stage S: butterflies j + i*W share b % Ns when Ns <= W
@@ -263,10 +281,10 @@ struct GroupFft {
   __device__ __forceinline__ v2f twiddle(const v2f* tl, int i, int q) const {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     const int ib = (Ns <= W) ? 0 : i;
-    if constexpr (TWG) {
+    if constexpr (tw_fetched(S)) {
       return tl[ib * (r - 1) + q - 1];
     } else {
-      return twr[tw_offset(N, R, RX, S) + ib * (r - 1) + q - 1];
+      return twr[tw_off(S) + ib * (r - 1) + q - 1];
     }
   }
 
@@ -274,8 +292,8 @@ struct GroupFft {
   __device__ __forceinline__ void stage(v2f (&v)[B][R]) {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     constexpr int nb = R / r;
-    v2f tl[TWG && S > 0 ? stage_sets<S>() * (r - 1) : 1];
-    if constexpr (TWG && S > 0) fetch_stage_tw<S>(tl);
+    v2f tl[tw_fetched(S) ? stage_sets<S>() * (r - 1) : 1];
+    if constexpr (tw_fetched(S)) fetch_stage_tw<S>(tl);
     if constexpr (S > 0) {
       const int buf = DB ? par : 0;
 #pragma unroll
@@ -449,7 +467,7 @@ struct FusedEngine {
   static constexpr int Q = TP + PF;
   static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
   static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
-  using Fft = GroupFft<N, R, RX, G, B, DB, TWG>;
+  using Fft = GroupFft<N, R, RX, G, B, DB, TWG, UNIT && !POW>;   // the FFT pass keeps shared twiddle sets
 
   // Long tap windows keep their coefficients in LDS (TP x N floats after
   // the FFT planes, shared by the groups of the block) instead of TP x R
