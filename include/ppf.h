@@ -132,15 +132,17 @@ ppf_plan_t ppf_plan_ex(int n_channels, int taps, const void* coeffs, int coeff_t
 
 /*
  * ppf_set_stream - HIP stream (a hipStream_t passed as void*) on which the
- * plan's work is enqueued; NULL selects the null stream (the default).
- * Not thread-safe against concurrent ppf_execute on the same plan.
+ * calling host thread enqueues its work on this plan; NULL selects the null
+ * stream (the default). The binding belongs to the calling thread, not to
+ * the plan: the plan is not modified, and threads that bind different
+ * streams may use one plan at the same time.
  */
 int ppf_set_stream(ppf_plan_t plan, void* hip_stream);
 
 /*
  * ppf_plan_set_path - force a path before the plan is used (tests and
  * benchmarks). PPF_ERR_UNSUPPORTED if the path does not exist for N, T.
- * Not thread-safe; call before the first ppf_execute.
+ * The one call that changes a plan: make it before the plan is shared.
  */
 int ppf_plan_set_path(ppf_plan_t plan, int path);
 
@@ -154,9 +156,10 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value);
  * out: device pointer, nspectra * N complex FP32 spectra, out[m*N + k] = X[m][k].
  * Both 16-byte aligned (else PPF_ERR_ALIGN) and non-overlapping (else
  * PPF_ERR_INVALID). nspectra == 0 is a successful no-op; nspectra < 0 is
- * PPF_ERR_INVALID. Concurrent calls on one plan with different streams
- * are safe only on the fused path (the two-pass path shares the plan's
- * workspace).
+ * PPF_ERR_INVALID. The work goes to the calling thread's stream for the
+ * plan (ppf_set_stream). Calls from several threads on one plan are safe:
+ * the two-pass path keeps one device workspace (128 MiB) per HIP stream,
+ * allocated on that stream's first two-pass call and freed with the plan.
  */
 int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
 
@@ -181,7 +184,8 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
  * valid until then and should be page-locked (hipHostMalloc) for the
  * copies to run asynchronously at full rate.
  * Errors as ppf_execute, plus PPF_ERR_NOMEM for the staging buffers.
- * Not thread-safe against other calls on the same plan.
+ * The staging buffers belong to the plan: one ppf_execute_host at a time
+ * per plan (other entry points may run beside it).
  */
 int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long long nspectra,
                      long long chunk_spectra);
@@ -195,13 +199,16 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
  * in:        device pointer, (nspectra + T - 1) * N samples of the input type.
  * out_power: device pointer, (nspectra / K) * N floats,
  *            out_power[j*N + k] = sum_{i<K} |X[j*K + i][k]|^2.
- * K >= 1 and nspectra a multiple of K (else PPF_ERR_INVALID). Alignment,
- * overlap and nspectra rules as ppf_execute. Plans in the matrix-core mode
- * return PPF_ERR_UNSUPPORTED.
+ * K >= 1 and nspectra a multiple of K (else PPF_ERR_INVALID). K above 2^28,
+ * or K*N above 2^24 on the two-pass path (whole groups of K spectra pass
+ * through its workspace), is PPF_ERR_UNSUPPORTED. Alignment, overlap and
+ * nspectra rules as ppf_execute. Plans in the matrix-core mode return
+ * PPF_ERR_UNSUPPORTED.
  */
 int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K);
 
-/* ppf_destroy - wait for the plan's stream, then free the plan. NULL is a no-op. */
+/* ppf_destroy - wait for every HIP stream the plan has run on, then free the
+ * plan. No other call may use the plan meanwhile. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);
 
 /*
@@ -264,23 +271,32 @@ typedef struct ppf_chunk {
 
 /* ppf_stream_create - new stream on `plan` with a zero history. The plan must
  * outlive the stream. Allocates 2*(T-1)*N samples of device memory.
- * Returns NULL on error. */
+ * Returns NULL on error. (Streams served by a server come from
+ * ppf_server_open_stream instead.) */
 ppf_stream_t ppf_stream_create(ppf_plan_t plan);
 
-/* ppf_stream_push - enqueue one chunk on the plan's HIP stream (asynchronous).
- * Pushes to one stream are processed in order. nspectra == 0 is a no-op. */
+/* ppf_stream_push - process one chunk, asynchronously. A stream from
+ * ppf_stream_create enqueues it on the calling thread's HIP stream for the
+ * plan (ppf_set_stream); a server stream queues it at its server (as
+ * ppf_server_submit with arrival time "now"). Pushes to one stream are
+ * processed in order; push to one stream from one thread at a time.
+ * nspectra == 0 is a no-op. */
 int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk);
 
 /* ppf_stream_get_history / ppf_stream_set_history - copy the (T-1)*N-sample
- * history to / from host memory (synchronous: waits for the plan's stream).
- * Saving and restoring it resumes a stream exactly (checkpoint/restore). */
+ * history to / from host memory (synchronous: waits for the stream's latest
+ * push). Saving and restoring it resumes a stream exactly
+ * (checkpoint/restore). Server streams: PPF_ERR_UNSUPPORTED. */
 int ppf_stream_get_history(ppf_stream_t stream, void* host_dst);
 int ppf_stream_set_history(ppf_stream_t stream, const void* host_src);
 
 /* Spectra pushed so far. */
 long long ppf_stream_position(ppf_stream_t stream);
 
-/* ppf_stream_destroy - wait for the plan's stream, free the history. NULL is a no-op. */
+/* ppf_stream_destroy - wait for the stream's chunks, free its history and the
+ * handle. For a server stream: close it, wait until its chunks are done
+ * (PPF_ERR_BUSY or PPF_ERR_HIP, after freeing the handle, if the server
+ * failed or stopped first), release its state. NULL is a no-op. */
 int ppf_stream_destroy(ppf_stream_t stream);
 
 /* ------------------------------------------------------------------------
@@ -299,7 +315,7 @@ int ppf_stream_destroy(ppf_stream_t stream);
 
 typedef struct ppf_server_s* ppf_server_t;
 
-typedef struct ppf_server_stats {
+typedef struct ppf_server_stats_s {
     long long chunks_done;        /* chunks completed since the last reset */
     long long spectra_done;
     long long bytes_in_done;      /* input bytes of completed chunks */
@@ -308,15 +324,17 @@ typedef struct ppf_server_stats {
     long long rejected;           /* open requests refused for budget */
     long long queued_admissions;  /* open requests that had to wait for budget */
     long long state_bytes_used;   /* budget in use: admitted streams + server buffers */
+    long long tags_dropped;       /* completed tags dropped unpolled (beyond 2^22 kept) */
     double p50_us, p99_us, max_us, mean_us;  /* chunk latency: completion seen on the
-                                               host minus arrival time */
+                                               host minus arrival time (percentiles
+                                               from a histogram of 0.4% bins) */
     double elapsed_s;             /* first arrival to last completion */
     double input_gbps;            /* bytes_in_done / elapsed_s / 1e9 */
     double mean_batch_chunks;
     double mean_batch_gpu_us;     /* device time of a batch graph (timing events) */
     double mean_form_us;          /* host time to form a batch */
-    double mean_launch_us;        /* host time of a graph launch */
-} ppf_server_stats;
+    double mean_launch_us;        /* host time of the descriptor upload and graph launch */
+} ppf_server_stats_t;
 
 /* Host steady clock in nanoseconds (the time base of arrival times). */
 long long ppf_clock_ns(void);
@@ -328,40 +346,71 @@ long long ppf_clock_ns(void);
  * descriptor tables. Returns NULL on error. */
 ppf_server_t ppf_server_create(size_t hbm_budget_bytes, int max_inflight);
 
-/* ppf_server_open_stream - open a stream on a complex-FP32 plan (at most 8
- * distinct plans per server; plans must outlive the server). If the state
- * does not fit the budget: PPF_ERR_BUDGET when wait_for_budget is 0, else
- * the stream is queued and admitted, in order, when closing streams free
- * budget; chunks may be submitted meanwhile and run once it is admitted. */
-int ppf_server_open_stream(ppf_server_t server, ppf_plan_t plan, int wait_for_budget, int* stream_id);
+/* Flags of ppf_server_open_stream_ex. */
+enum ppf_open_flags {
+    PPF_OPEN_QUEUE = 0,  /* wait in line for budget (ppf_server_open_stream) */
+    PPF_OPEN_NOWAIT = 1  /* PPF_ERR_BUDGET instead of waiting */
+};
 
-/* 1 if the stream has been admitted, 0 if it is still waiting, <0 on error. */
-int ppf_server_stream_admitted(ppf_server_t server, int stream_id);
+/*
+ * ppf_server_open_stream - open a stream of `plan` on the server; *out gets
+ * its handle, fed with ppf_stream_push (or ppf_server_submit) and released
+ * with ppf_stream_destroy. The plan must be complex FP32 with FP32 DFT
+ * stages (else PPF_ERR_UNSUPPORTED), at most 8 distinct plans per server,
+ * and plans must outlive the server. The stream's state is two
+ * (T-1)*N-sample history buffers plus 4 KiB. If it does not fit the budget
+ * now, the stream waits in line and is admitted, in order, when closing
+ * streams free budget; chunks pushed meanwhile run once it is admitted.
+ * PPF_ERR_BUDGET if the state can never fit (beyond the budget left after
+ * the server's own buffers).
+ */
+int ppf_server_open_stream(ppf_server_t server, ppf_plan_t plan, ppf_stream_t* out);
 
-/* ppf_server_submit - queue one chunk of a stream (thread-safe). Chunks of a
- * stream are processed in submission order. arrival_ns is the chunk's
- * arrival time on ppf_clock_ns (< 0: now); latency is measured from it.
- * Device buffers must stay valid until the chunk's tag is returned by
- * ppf_server_poll or ppf_server_drain returns. */
-int ppf_server_submit(ppf_server_t server, int stream_id, const ppf_chunk* chunk, long long arrival_ns);
+/* ppf_server_open_stream_ex - as ppf_server_open_stream; with PPF_OPEN_NOWAIT
+ * a stream that does not fit now is refused (PPF_ERR_BUDGET). */
+int ppf_server_open_stream_ex(ppf_server_t server, ppf_plan_t plan, int flags, ppf_stream_t* out);
+
+/* 1 if the server stream has been admitted, 0 if it is still waiting, <0 on error. */
+int ppf_server_stream_admitted(ppf_stream_t stream);
+
+/* ppf_server_submit - ppf_stream_push with an explicit arrival time:
+ * arrival_ns on ppf_clock_ns (< 0: now), from which the chunk's latency is
+ * measured. Lock-free for the caller (it waits only while 65536 chunks are
+ * queued ahead of the scheduler). A chunk of any size up to 2^31 spectra is
+ * taken: one larger than a batch can hold (e.g. 16384 spectra at N=4096
+ * two-pass) runs as consecutive pieces, and its tag is reported once, when
+ * the last piece is done. Device buffers must stay valid until the tag is
+ * returned by ppf_server_poll (or ppf_server_drain returns). */
+int ppf_server_submit(ppf_stream_t stream, const ppf_chunk* chunk, long long arrival_ns);
 
 /* ppf_server_poll - copy up to max completed chunk tags, in completion
- * order; returns the number copied (>= 0) or an error. */
+ * order; returns the number copied (>= 0) or an error. The server keeps the
+ * latest 2^22 unpolled tags (older ones are counted in tags_dropped). */
 int ppf_server_poll(ppf_server_t server, unsigned long long* tags, int max);
 
 /* ppf_server_drain - wait until every submitted chunk has completed;
  * PPF_ERR_BUSY after timeout_s seconds. */
 int ppf_server_drain(ppf_server_t server, double timeout_s);
 
-/* ppf_server_close_stream - no further submissions; the state is released
- * once the stream's chunks have completed. */
-int ppf_server_close_stream(ppf_server_t server, int stream_id);
+/* ppf_server_close_stream - no further pushes. An admitted stream's pushed
+ * chunks still run, and its budget is given back as soon as they are done;
+ * a stream closed while waiting for admission leaves the line and its
+ * pushed chunks are dropped (their tags are never returned). The handle
+ * stays valid until ppf_stream_destroy. */
+int ppf_server_close_stream(ppf_stream_t stream);
 
-int ppf_server_get_stats(ppf_server_t server, ppf_server_stats* out);
+/* ppf_server_stats - chunk latency p50 and p99 (us) and sustained input
+ * GB/s since the last reset; any pointer may be NULL. */
+int ppf_server_stats(ppf_server_t server, double* p50_us, double* p99_us, double* gbps);
+
+/* ppf_server_get_stats - every counter above. */
+int ppf_server_get_stats(ppf_server_t server, ppf_server_stats_t* out);
 int ppf_server_reset_stats(ppf_server_t server);
 
-/* ppf_server_destroy - finish outstanding chunks, stop the scheduler, free
- * everything. NULL is a no-op. */
+/* ppf_server_destroy - finish outstanding chunks of admitted streams (chunks
+ * of streams still waiting for admission are dropped), stop the scheduler,
+ * free everything. Stream handles of the server that are still open then
+ * accept only ppf_stream_destroy. NULL is a no-op. */
 int ppf_server_destroy(ppf_server_t server);
 
 /* Status of the most recent failure on this host thread (PPF_OK if none). */

@@ -63,6 +63,7 @@ def build(jobs: int = 4, verbose: bool = False, defines=(), out: pathlib.Path | 
     lib = pathlib.Path(out) if out else LIB
     bdir = BUILD if out is None else BUILD / lib.stem
     bdir.mkdir(parents=True, exist_ok=True)
+    lib.parent.mkdir(parents=True, exist_ok=True)
     extra = [f"-D{d}" for d in defines]
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, extra, bdir), SOURCES))

@@ -6,11 +6,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -97,6 +99,22 @@ constexpr size_t kWorkspaceBytes = (size_t)PPF_WORKSPACE_MIB << 20;
 #endif
 constexpr int kHostStages = PPF_HOST_STAGES;
 
+// Detection: a fused launch integrates whole groups of K spectra of at most
+// 2^28 spectra; the two-pass form passes whole groups through its
+// workspace (2^24 samples).
+constexpr int kMaxPowerK = 1 << 28;
+constexpr long long kMaxPowerKN = 1ll << 24;
+
+// Every plan has a process-unique id; a host thread's stream binding for a
+// plan is kept under that id (ppf_set_stream), so a plan object is never
+// written by ppf_set_stream and threads may share it.
+std::atomic<unsigned long long> g_next_plan_id{1};
+struct StreamBinding {
+  unsigned long long plan_id;
+  hipStream_t stream;
+};
+thread_local std::vector<StreamBinding> t_bindings;
+
 }  // namespace
 
 struct ppf_plan_s {
@@ -109,8 +127,18 @@ struct ppf_plan_s {
   void* d_coef16 = nullptr;    // matrix-core mode: FP16 coefficients in lane order
   void* d_w256 = nullptr;      // matrix-core mode: FP16 values exp(-2 pi i k/256)
   int mfma_e1 = 0;             // matrix-core mode: samples are scaled by 2^-e1
-  void* d_ws = nullptr;
-  size_t ws_bytes = 0;
+  unsigned long long id = 0;
+  // Two-pass workspaces, one per HIP stream the plan has run on, so calls
+  // on different streams never share one; guarded by mu.
+  struct Workspace {
+    hipStream_t stream;
+    void* ptr;
+    size_t bytes;
+    long long spectra;
+  };
+  std::mutex mu;
+  std::vector<Workspace> ws;
+  std::vector<hipStream_t> used_streams;   // streams to wait for in ppf_destroy
   // single mode (host-resident data): staging buffers, copy streams, events
   void* h_in[kHostStages] = {};
   void* h_out[kHostStages] = {};
@@ -118,8 +146,20 @@ struct ppf_plan_s {
   hipStream_t h2d = nullptr, d2h = nullptr;
   hipEvent_t ev_in[kHostStages] = {}, ev_comp[kHostStages] = {}, ev_out[kHostStages] = {};
   hipEvent_t ev_start = nullptr;
-  long long chunk_spectra = 0;
-  hipStream_t stream = nullptr;
+
+  // the calling thread's stream for this plan (ppf_set_stream), also
+  // remembered for ppf_destroy
+  hipStream_t stream() {
+    for (const StreamBinding& b : t_bindings)
+      if (b.plan_id == id) return b.stream;
+    return nullptr;
+  }
+  void note_stream(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (hipStream_t u : used_streams)
+      if (u == st) return;
+    used_streams.push_back(st);
+  }
 
   ppf::PlanDev dev() const {
     ppf::PlanDev p;
@@ -146,7 +186,7 @@ struct ppf_plan_s {
     if (d_coef) (void)hipFree(d_coef);
     if (d_ones) (void)hipFree(d_ones);
     if (d_tw) (void)hipFree(d_tw);
-    if (d_ws) (void)hipFree(d_ws);
+    for (const Workspace& w : ws) (void)hipFree(w.ptr);
     for (int i = 0; i < kHostStages; ++i) {
       if (h_in[i]) (void)hipFree(h_in[i]);
       if (h_out[i]) (void)hipFree(h_out[i]);
@@ -162,62 +202,80 @@ struct ppf_plan_s {
   }
 };
 
-struct ppf_stream_s {
-  ppf_plan_t plan = nullptr;
-  void* hist[2] = {nullptr, nullptr};   // ping-pong history buffers, (T-1)*N samples each
-  int cur = 0;
-  long long hist_samples = 0;
-  long long pushed_spectra = 0;
-  ~ppf_stream_s() {
-    if (hist[0]) (void)hipFree(hist[0]);
-    if (hist[1]) (void)hipFree(hist[1]);
-  }
-};
+ppf_stream_s::~ppf_stream_s() {
+  if (hist[0]) (void)hipFree(hist[0]);
+  if (hist[1]) (void)hipFree(hist[1]);
+}
 
 namespace {
 
-int ensure_workspace(ppf_plan_t p, long long min_spectra = 1) {
-  if (p->d_ws && p->chunk_spectra >= min_spectra) return PPF_OK;
-  if (p->d_ws) {   // grow: earlier work on the plan's stream may still read it
-    const hipError_t es = hipStreamSynchronize(p->stream);
+// The two-pass workspace of HIP stream `st` (at least min_spectra spectra),
+// allocated on the stream's first two-pass call. Work on one stream runs in
+// order, so calls on that stream may reuse it; other streams have their own.
+int ensure_workspace(ppf_plan_t p, hipStream_t st, long long min_spectra, void** ptr, long long* spectra) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  ppf_plan_s::Workspace* w = nullptr;
+  for (ppf_plan_s::Workspace& x : p->ws)
+    if (x.stream == st) w = &x;
+  if (w && w->spectra >= min_spectra) {
+    *ptr = w->ptr;
+    *spectra = w->spectra;
+    return PPF_OK;
+  }
+  if (w) {   // grow: earlier work on this stream may still read it
+    const hipError_t es = hipStreamSynchronize(st);
     if (es != hipSuccess) return fail_hip(es, "workspace synchronize");
-    (void)hipFree(p->d_ws);
-    p->d_ws = nullptr;
+    (void)hipFree(w->ptr);
+    w->ptr = nullptr;
   }
   long long k = (long long)(kWorkspaceBytes / (8ull * p->N));
   if (k < min_spectra) k = min_spectra;
   if (k < 1) k = 1;
-  p->chunk_spectra = k;
-  p->ws_bytes = (size_t)k * p->N * 8;
-  hipError_t e = hipMalloc(&p->d_ws, p->ws_bytes);
+  void* d = nullptr;
+  const size_t bytes = (size_t)k * p->N * 8;
+  hipError_t e = hipMalloc(&d, bytes);
   if (e != hipSuccess) {
-    p->d_ws = nullptr;
-    p->ws_bytes = 0;
+    if (w) {
+      *w = p->ws.back();
+      p->ws.pop_back();
+    }
     return fail_hip(e, "workspace allocation");
   }
+  if (!w) {
+    p->ws.push_back(ppf_plan_s::Workspace{st, nullptr, 0, 0});
+    w = &p->ws.back();
+  }
+  w->ptr = d;
+  w->bytes = bytes;
+  w->spectra = k;
+  *ptr = d;
+  *spectra = k;
   return PPF_OK;
 }
 
 // FIR + FFT over M spectra of the concatenation x0 (h0 blocks) ++ x1.
-int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* out, long long M) {
+int run_batch(ppf_plan_t p, hipStream_t stream, const void* x0, long long h0, const void* x1, void* out,
+              long long M) {
   const ppf::PlanDev pd = p->dev();
   const size_t sb = (size_t)sample_bytes(p->in_type);
   if (p->fft_mode == PPF_FFT_MFMA_F16) {
     ppf::BatchArgs a{x0, x1, h0, out, M};
-    hipError_t e = ppf::launch_mfma(p->mfma(), a, p->stream);
+    hipError_t e = ppf::launch_mfma(p->mfma(), a, stream);
     if (e != hipSuccess) return fail_hip(e, "matrix-core kernel launch");
     return PPF_OK;
   }
   if (p->path == PPF_PATH_FUSED) {
     ppf::BatchArgs a{x0, x1, h0, out, M};
-    hipError_t e = ppf::launch_fused(pd, a, p->stream);
+    hipError_t e = ppf::launch_fused(pd, a, stream);
     if (e != hipSuccess) return fail_hip(e, "fused kernel launch");
     return PPF_OK;
   }
-  int st = ensure_workspace(p);
+  void* ws = nullptr;
+  long long chunk = 0;
+  int st = ensure_workspace(p, stream, 1, &ws, &chunk);
   if (st != PPF_OK) return st;
-  for (long long c0 = 0; c0 < M; c0 += p->chunk_spectra) {
-    const long long k = (M - c0 < p->chunk_spectra) ? (M - c0) : p->chunk_spectra;
+  for (long long c0 = 0; c0 < M; c0 += chunk) {
+    const long long k = (M - c0 < chunk) ? (M - c0) : chunk;
     // blocks c0 .. of the concatenation: split between x0 and x1
     ppf::BatchArgs a;
     if (c0 < h0) {
@@ -229,44 +287,46 @@ int run_batch(ppf_plan_t p, const void* x0, long long h0, const void* x1, void* 
       a.h0 = 0;
       a.x1 = (const char*)x1 + (size_t)(c0 - h0) * pd.N * sb;
     }
-    a.out = p->d_ws;
+    a.out = ws;
     a.M = k;
-    hipError_t e = ppf::launch_fir(pd, a, p->stream);
+    hipError_t e = ppf::launch_fir(pd, a, stream);
     if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
-    e = ppf::launch_fft(pd, p->d_ws, (char*)out + (size_t)c0 * pd.N * 8, k, p->stream);
+    e = ppf::launch_fft(pd, ws, (char*)out + (size_t)c0 * pd.N * 8, k, stream);
     if (e != hipSuccess) return fail_hip(e, "FFT kernel launch");
   }
   return PPF_OK;
 }
 
 // Detection: |X|^2 summed over K spectra, M a multiple of K.
-int run_power(ppf_plan_t p, const void* in, float* pout, long long M, int K) {
+int run_power(ppf_plan_t p, hipStream_t stream, const void* in, float* pout, long long M, int K) {
   const ppf::PlanDev pd = p->dev();
   const size_t sb = (size_t)sample_bytes(p->in_type);
   if (p->path == PPF_PATH_FUSED) {
     ppf::BatchArgs a{in, in, 0, nullptr, M};
-    hipError_t e = ppf::launch_fused_power(pd, a, pout, K, p->stream);
+    hipError_t e = ppf::launch_fused_power(pd, a, pout, K, stream);
     if (e != hipSuccess) return fail_hip(e, "fused power kernel launch");
     return PPF_OK;
   }
   // two-pass: chunks of whole groups of K spectra
-  int st = ensure_workspace(p, K);
+  void* ws = nullptr;
+  long long wsk = 0;
+  int st = ensure_workspace(p, stream, K, &ws, &wsk);
   if (st != PPF_OK) return st;
-  const long long chunk = p->chunk_spectra / K * K;
+  const long long chunk = wsk / K * K;
   for (long long c0 = 0; c0 < M; c0 += chunk) {
     const long long k = (M - c0 < chunk) ? (M - c0) : chunk;
     ppf::BatchArgs a{(const char*)in + (size_t)c0 * pd.N * sb, (const char*)in + (size_t)c0 * pd.N * sb, 0,
-                     p->d_ws, k};
-    hipError_t e = ppf::launch_fir(pd, a, p->stream);
+                     ws, k};
+    hipError_t e = ppf::launch_fir(pd, a, stream);
     if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
-    e = ppf::launch_fft_power(pd, p->d_ws, pout + (size_t)(c0 / K) * pd.N, k, K, p->stream);
+    e = ppf::launch_fft_power(pd, ws, pout + (size_t)(c0 / K) * pd.N, k, K, stream);
     if (e != hipSuccess) return fail_hip(e, "FFT power kernel launch");
   }
   return PPF_OK;
 }
 
 // Single mode: staging buffers for chunks of `chunk` spectra (grown on demand).
-int ensure_host_pipe(ppf_plan_t p, long long chunk) {
+int ensure_host_pipe(ppf_plan_t p, hipStream_t stream, long long chunk) {
   const size_t sb = (size_t)sample_bytes(p->in_type);
   const size_t in_need = (size_t)(chunk + p->T - 1) * p->N * sb;
   const size_t out_need = (size_t)chunk * p->N * 8;
@@ -284,7 +344,7 @@ int ensure_host_pipe(ppf_plan_t p, long long chunk) {
   }
   if (p->h_in_cap < in_need || p->h_out_cap < out_need) {
     // earlier work on the staging buffers must be finished before they go
-    for (hipStream_t st : {p->stream, p->h2d, p->d2h}) {
+    for (hipStream_t st : {stream, p->h2d, p->d2h}) {
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return fail_hip(e, "single-mode synchronize");
     }
@@ -359,6 +419,7 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   p->coeff_shift = coeff_shift;
   p->fft_mode = fft_mode;
   p->path = (fft_mode == PPF_FFT_MFMA_F16 || fused_ok_for(N, TP, in_type)) ? PPF_PATH_FUSED : PPF_PATH_TWO_PASS;
+  p->id = g_next_plan_id.fetch_add(1);
 
   // coefficients padded at the front with TP-T zero segments; FP16
   // coefficients are widened exactly and the 2^-shift is applied (exact)
@@ -457,7 +518,18 @@ ppf_plan_t ppf_plan_ex(int n_channels, int taps, const void* coeffs, int coeff_t
 
 int ppf_set_stream(ppf_plan_t plan, void* hip_stream) {
   if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
-  plan->stream = (hipStream_t)hip_stream;
+  try {
+    for (StreamBinding& b : t_bindings)
+      if (b.plan_id == plan->id) {
+        b.stream = (hipStream_t)hip_stream;
+        return PPF_OK;
+      }
+    // bindings of destroyed plans are dropped now and then
+    if (t_bindings.size() >= 64) t_bindings.erase(t_bindings.begin());
+    t_bindings.push_back(StreamBinding{plan->id, (hipStream_t)hip_stream});
+  } catch (...) {
+    return fail(PPF_ERR_NOMEM, "host allocation");
+  }
   return PPF_OK;
 }
 
@@ -490,7 +562,13 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value) {
     case PPF_Q_N: *value = plan->N; return PPF_OK;
     case PPF_Q_TAPS: *value = plan->T; return PPF_OK;
     case PPF_Q_PATH: *value = plan->path; return PPF_OK;
-    case PPF_Q_WORKSPACE_BYTES: *value = (long long)plan->ws_bytes; return PPF_OK;
+    case PPF_Q_WORKSPACE_BYTES: {
+      std::lock_guard<std::mutex> lk(plan->mu);
+      long long total = 0;
+      for (const ppf_plan_s::Workspace& w : plan->ws) total += (long long)w.bytes;
+      *value = total;
+      return PPF_OK;
+    }
     case PPF_Q_IN_TYPE: *value = plan->in_type; return PPF_OK;
     case PPF_Q_FFT_MODE: *value = plan->fft_mode; return PPF_OK;
     case PPF_Q_COEFF_SHIFT: *value = plan->coeff_shift; return PPF_OK;
@@ -512,7 +590,9 @@ int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra) 
     const size_t in_bytes = (size_t)(nspectra + plan->T - 1) * plan->N * sb;
     const size_t out_bytes = (size_t)nspectra * plan->N * 8;
     if (overlaps((uintptr_t)in, in_bytes, (uintptr_t)out, out_bytes)) return fail(PPF_ERR_INVALID, "in and out overlap");
-    const int st = run_batch(plan, in, 0, in, out, nspectra);
+    const hipStream_t stream = plan->stream();
+    plan->note_stream(stream);
+    const int st = run_batch(plan, stream, in, 0, in, out, nspectra);
     if (st == PPF_OK) g_status = PPF_OK;
     return st;
   } catch (...) {
@@ -524,6 +604,9 @@ int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long lo
   try {
     if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
     if (K < 1) return fail(PPF_ERR_INVALID, "K=%d must be >= 1", K);
+    if (K > kMaxPowerK) return fail(PPF_ERR_UNSUPPORTED, "K=%d exceeds 2^28", K);
+    if (plan->path == PPF_PATH_TWO_PASS && (long long)K * plan->N > kMaxPowerKN)
+      return fail(PPF_ERR_UNSUPPORTED, "two-pass detection takes K*N <= 2^24 (K=%d, N=%d)", K, plan->N);
     if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
     if (nspectra % K) return fail(PPF_ERR_INVALID, "nspectra=%lld is not a multiple of K=%d", nspectra, K);
     if (plan->fft_mode == PPF_FFT_MFMA_F16)
@@ -537,7 +620,9 @@ int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long lo
     const size_t out_bytes = (size_t)(nspectra / K) * plan->N * 4;
     if (overlaps((uintptr_t)in, in_bytes, (uintptr_t)out_power, out_bytes))
       return fail(PPF_ERR_INVALID, "in and out_power overlap");
-    const int st = run_power(plan, in, out_power, nspectra, K);
+    const hipStream_t stream = plan->stream();
+    plan->note_stream(stream);
+    const int st = run_power(plan, stream, in, out_power, nspectra, K);
     if (st == PPF_OK) g_status = PPF_OK;
     return st;
   } catch (...) {
@@ -562,10 +647,12 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
     long long chunk = chunk_spectra > 0 ? chunk_spectra : (long long)(((size_t)PPF_HOST_CHUNK_MIB << 20) / ((size_t)N * sb));
     if (chunk < 1) chunk = 1;
     if (chunk > nspectra) chunk = nspectra;
-    int st = ensure_host_pipe(plan, chunk);
+    const hipStream_t stream = plan->stream();
+    plan->note_stream(stream);
+    int st = ensure_host_pipe(plan, stream, chunk);
     if (st != PPF_OK) return st;
     // the copy streams start after what the plan's stream already holds
-    hipError_t e = hipEventRecord(plan->ev_start, plan->stream);
+    hipError_t e = hipEventRecord(plan->ev_start, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->h2d, plan->ev_start, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->d2h, plan->ev_start, 0);
     const long long nch = (nspectra + chunk - 1) / chunk;
@@ -581,12 +668,12 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
         e = hipMemcpyAsync(plan->h_in[b], (const char*)host_in + (size_t)m0 * N * sb, kin, hipMemcpyHostToDevice,
                            plan->h2d);
       if (e == hipSuccess) e = hipEventRecord(plan->ev_in[b], plan->h2d);
-      if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in[b], 0);
-      if (e == hipSuccess && i >= kHostStages) e = hipStreamWaitEvent(plan->stream, plan->ev_out[b], 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, plan->ev_in[b], 0);
+      if (e == hipSuccess && i >= kHostStages) e = hipStreamWaitEvent(stream, plan->ev_out[b], 0);
       if (e != hipSuccess) break;
-      st = run_batch(plan, plan->h_in[b], 0, plan->h_in[b], plan->h_out[b], k);
+      st = run_batch(plan, stream, plan->h_in[b], 0, plan->h_in[b], plan->h_out[b], k);
       if (st != PPF_OK) return st;
-      e = hipEventRecord(plan->ev_comp[b], plan->stream);
+      e = hipEventRecord(plan->ev_comp[b], stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(plan->d2h, plan->ev_comp[b], 0);
       if (e == hipSuccess)
         e = hipMemcpyAsync((char*)host_out + (size_t)m0 * N * 8, plan->h_out[b], (size_t)k * N * 8,
@@ -594,7 +681,7 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
       if (e == hipSuccess) e = hipEventRecord(plan->ev_out[b], plan->d2h);
     }
     // the plan's stream completes after the last copy back
-    if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_out[(nch - 1) % kHostStages], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, plan->ev_out[(nch - 1) % kHostStages], 0);
     if (e != hipSuccess) return fail_hip(e, "single-mode pipeline");
     g_status = PPF_OK;
     return PPF_OK;
@@ -655,7 +742,12 @@ int ppf_destroy(ppf_plan_t plan) {
   if (!plan) return PPF_OK;
   if (plan->h2d) (void)hipStreamSynchronize(plan->h2d);
   if (plan->d2h) (void)hipStreamSynchronize(plan->d2h);
-  hipError_t e = hipStreamSynchronize(plan->stream);
+  // every stream the plan has run on, and the caller's
+  hipError_t e = hipStreamSynchronize(plan->stream());
+  for (hipStream_t st : plan->used_streams) {
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+  }
   delete plan;
   if (e != hipSuccess) return fail_hip(e, "ppf_destroy synchronize");
   return PPF_OK;
@@ -688,6 +780,7 @@ ppf_stream_t ppf_stream_create(ppf_plan_t plan) {
 int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk) {
   try {
     if (!stream || !chunk) return fail(PPF_ERR_INVALID, "stream or chunk is NULL");
+    if (stream->server_stream) return ppf_internal_server_push(stream, chunk, -1);
     ppf_plan_t plan = stream->plan;
     const long long S = chunk->nspectra;
     if (S < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", S);
@@ -699,13 +792,20 @@ int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk) {
     if (overlaps((uintptr_t)chunk->in, (size_t)S * plan->N * sb, (uintptr_t)chunk->out, (size_t)S * plan->N * 8))
       return fail(PPF_ERR_INVALID, "chunk in and out overlap");
     const long long h0 = plan->T - 1;
+    const hipStream_t hs = plan->stream();
+    if (stream->last_stream != hs && stream->pushed_spectra > 0) {
+      // the previous push ran on another HIP stream: keep the pushes ordered
+      const hipError_t es = hipStreamSynchronize(stream->last_stream);
+      if (es != hipSuccess) return fail_hip(es, "stream synchronize");
+    }
+    plan->note_stream(hs);
+    stream->last_stream = hs;
     void* cur = stream->hist[stream->cur];
-    int st = run_batch(plan, cur, h0, chunk->in, chunk->out, S);
+    int st = run_batch(plan, hs, cur, h0, chunk->in, chunk->out, S);
     if (st != PPF_OK) return st;
     if (h0 > 0) {
       void* nxt = stream->hist[1 - stream->cur];
-      hipError_t e = ppf::launch_history(cur, chunk->in, nxt, stream->hist_samples, S * plan->N, (int)sb,
-                                         plan->stream);
+      hipError_t e = ppf::launch_history(cur, chunk->in, nxt, stream->hist_samples, S * plan->N, (int)sb, hs);
       if (e != hipSuccess) return fail_hip(e, "history kernel launch");
       stream->cur = 1 - stream->cur;
     }
@@ -719,10 +819,11 @@ int ppf_stream_push(ppf_stream_t stream, const ppf_chunk* chunk) {
 
 int ppf_stream_get_history(ppf_stream_t stream, void* host_dst) {
   if (!stream) return fail(PPF_ERR_INVALID, "stream is NULL");
+  if (stream->server_stream) return fail(PPF_ERR_UNSUPPORTED, "a server stream's history stays with the server");
   const size_t bytes = (size_t)stream->hist_samples * sample_bytes(stream->plan->in_type);
   if (bytes == 0) return PPF_OK;
   if (!host_dst) return fail(PPF_ERR_INVALID, "host_dst is NULL");
-  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  hipError_t e = hipStreamSynchronize(stream->last_stream);
   if (e != hipSuccess) return fail_hip(e, "history synchronize");
   e = hipMemcpy(host_dst, stream->hist[stream->cur], bytes, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e, "history copy");
@@ -732,10 +833,11 @@ int ppf_stream_get_history(ppf_stream_t stream, void* host_dst) {
 
 int ppf_stream_set_history(ppf_stream_t stream, const void* host_src) {
   if (!stream) return fail(PPF_ERR_INVALID, "stream is NULL");
+  if (stream->server_stream) return fail(PPF_ERR_UNSUPPORTED, "a server stream's history stays with the server");
   const size_t bytes = (size_t)stream->hist_samples * sample_bytes(stream->plan->in_type);
   if (bytes == 0) return PPF_OK;
   if (!host_src) return fail(PPF_ERR_INVALID, "host_src is NULL");
-  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  hipError_t e = hipStreamSynchronize(stream->last_stream);
   if (e != hipSuccess) return fail_hip(e, "history synchronize");
   e = hipMemcpy(stream->hist[stream->cur], host_src, bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail_hip(e, "history copy");
@@ -750,7 +852,8 @@ long long ppf_stream_position(ppf_stream_t stream) {
 
 int ppf_stream_destroy(ppf_stream_t stream) {
   if (!stream) return PPF_OK;
-  hipError_t e = hipStreamSynchronize(stream->plan->stream);
+  if (stream->server_stream) return ppf_internal_server_stream_destroy(stream);
+  hipError_t e = hipStreamSynchronize(stream->last_stream);
   delete stream;
   if (e != hipSuccess) return fail_hip(e, "ppf_stream_destroy synchronize");
   return PPF_OK;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+
 namespace ppf {
 
 // Launch description for one batch of spectra. The input is read as the
@@ -123,6 +125,33 @@ hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st);
 
 // Plan internals for the server (implemented beside the plan object).
 struct ppf_plan_s;
+struct ppf_server_s;
+struct ppf_chunk;
 ppf::PlanDev ppf_internal_plan_dev(const ppf_plan_s* plan);
 // Record a failure as the calling thread's last error.
 void ppf_internal_set_error(int status, const char* message);
+
+namespace ppf {
+struct SrvStream;   // a server's per-stream state (ppf_server.cpp)
+}
+
+// A stream handle. A plain stream owns its history and runs its chunks on
+// the plan's HIP stream; a server stream (server_stream true) hands its
+// chunks to the server, which owns the history.
+struct ppf_stream_s {
+  ppf_plan_s* plan = nullptr;
+  void* hist[2] = {nullptr, nullptr};   // ping-pong history buffers, (T-1)*N samples each
+  int cur = 0;
+  long long hist_samples = 0;
+  long long pushed_spectra = 0;
+  hipStream_t last_stream = nullptr;    // HIP stream of the latest push (plain streams)
+  bool server_stream = false;
+  ppf_server_s* server = nullptr;       // NULL once the server is destroyed
+  std::shared_ptr<ppf::SrvStream> srv;
+  ~ppf_stream_s();
+};
+
+// Server streams (ppf_server.cpp): a push queues the chunk at the server;
+// destroy closes the stream, waits for its chunks and frees the handle.
+int ppf_internal_server_push(ppf_stream_s* stream, const ppf_chunk* chunk, long long arrival_ns);
+int ppf_internal_server_stream_destroy(ppf_stream_s* stream);

@@ -10,6 +10,16 @@
 // submits each chunk at its scheduled arrival time and latency is measured
 // from that time, so a late producer counts against the server. Prints one
 // JSON line of throughput and latency.
+//
+// Checked mode (--check-dir D): the coefficients of every plan come from
+// D/coef_<N>_<T>.f32, and the streams listed in D/manifest.txt (lines
+// "index N T samples") take their N and T from there and read their first
+// `samples` input samples from D/in_<index>.c64 instead of the ring: their
+// chunks move forward through that input and through an output buffer of
+// the same length (nothing reused) until it is used up, after which they
+// fall back to the ring. After the run the filled output prefix of each
+// such stream is written to D/out_<index>.c64 and its spectrum count to
+// D/out_<index>.txt, for a comparison against a reference outside.
 
 #include <hip/hip_runtime.h>
 
@@ -20,7 +30,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
@@ -92,18 +104,37 @@ std::vector<float> sinc_hamming(int N, int T) {
 }
 
 struct Stream {
-  int id = -1;
+  ppf_stream_t h = nullptr;
   int N = 0, T = 0;
   float2* in = nullptr;
   float2* out = nullptr;
   long long ring_spectra = 0;
   long long in_pos = 0, out_pos = 0;   // spectra
+  // checked mode: a forward-only input and output of chk_spectra spectra
+  float2* chk_in = nullptr;
+  float2* chk_out = nullptr;
+  long long chk_spectra = 0, chk_pos = 0;
+  bool chk_done = false;
 };
 
 double arg_d(int argc, char** argv, const char* name, double def) {
   for (int i = 1; i + 1 < argc; ++i)
     if (!strcmp(argv[i], name)) return atof(argv[i + 1]);
   return def;
+}
+
+std::string arg_s(int argc, char** argv, const char* name) {
+  for (int i = 1; i + 1 < argc; ++i)
+    if (!strcmp(argv[i], name)) return argv[i + 1];
+  return "";
+}
+
+bool read_file(const std::string& path, void* dst, size_t bytes) {
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f) return false;
+  const size_t got = fread(dst, 1, bytes, f);
+  fclose(f);
+  return got == bytes;
 }
 
 }  // namespace
@@ -121,6 +152,24 @@ int main(int argc, char** argv) {
   // restrict the (N, T) mix: --only-n 1024 --only-t 8 (diagnostics)
   const int only_n = (int)arg_d(argc, argv, "--only-n", 0);
   const int only_t = (int)arg_d(argc, argv, "--only-t", 0);
+  const std::string check_dir = arg_s(argc, argv, "--check-dir");
+  // checked streams: index -> (N, T, samples)
+  std::map<int, std::vector<long long>> checked;
+  if (!check_dir.empty()) {
+    std::ifstream mf(check_dir + "/manifest.txt");
+    if (!mf) {
+      fprintf(stderr, "cannot read %s/manifest.txt\n", check_dir.c_str());
+      return 5;
+    }
+    long long idx, n, t, samples;
+    while (mf >> idx >> n >> t >> samples) {
+      if (idx < 0 || idx >= nstreams || n <= 0 || t <= 0 || samples <= 0 || samples % n) {
+        fprintf(stderr, "bad manifest line %lld %lld %lld %lld\n", idx, n, t, samples);
+        return 5;
+      }
+      checked[(int)idx] = {n, t, samples};
+    }
+  }
 
   CK(hipSetDevice(0));
   int Ns[3] = {256, 1024, 4096};
@@ -134,10 +183,22 @@ int main(int argc, char** argv) {
     Rng r(seed + 1000ull * (uint64_t)i);
     streams[i].N = Ns[r.range(0, 2)];
     streams[i].T = Ts[r.range(0, 1)];
+    if (checked.count(i)) {
+      streams[i].N = (int)checked[i][0];
+      streams[i].T = (int)checked[i][1];
+    }
     mean_n += streams[i].N;
     auto key = std::make_pair(streams[i].N, streams[i].T);
     if (!plans.count(key)) {
       std::vector<float> h = sinc_hamming(key.first, key.second);
+      if (!check_dir.empty()) {
+        const std::string cf = check_dir + "/coef_" + std::to_string(key.first) + "_" + std::to_string(key.second) +
+                               ".f32";
+        if (!read_file(cf, h.data(), h.size() * sizeof(float))) {
+          fprintf(stderr, "cannot read %s\n", cf.c_str());
+          return 5;
+        }
+      }
       ppf_plan_t p = ppf_plan(key.first, key.second, h.data());
       if (!p) PK(ppf_last_error());
       plans[key] = p;
@@ -156,7 +217,21 @@ int main(int argc, char** argv) {
     hipLaunchKernelGGL(fill_gaussian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, st.in, n,
                        (unsigned long long)(seed * 7919ull + i));
     CK(hipGetLastError());
-    PK(ppf_server_open_stream(srv, plans[std::make_pair(st.N, st.T)], 0, &st.id));
+    if (checked.count(i)) {
+      st.chk_spectra = checked[i][2] / st.N;
+      const size_t bytes = (size_t)checked[i][2] * sizeof(float2);
+      std::vector<float2> host((size_t)checked[i][2]);
+      const std::string inf = check_dir + "/in_" + std::to_string(i) + ".c64";
+      if (!read_file(inf, host.data(), bytes)) {
+        fprintf(stderr, "cannot read %s\n", inf.c_str());
+        return 5;
+      }
+      CK(hipMalloc(&st.chk_in, bytes));
+      CK(hipMalloc(&st.chk_out, bytes));
+      CK(hipMemcpy(st.chk_in, host.data(), bytes, hipMemcpyHostToDevice));
+      CK(hipMemset(st.chk_out, 0xFF, bytes));   // NaN until written
+    }
+    PK(ppf_server_open_stream_ex(srv, plans[std::make_pair(st.N, st.T)], PPF_OPEN_NOWAIT, &st.h));
   }
   CK(hipDeviceSynchronize());
 
@@ -189,43 +264,69 @@ int main(int argc, char** argv) {
     }
     Stream& st = streams[arr.range(0, nstreams - 1)];
     const int S = arr.range(1, max_s);
-    if (st.in_pos + S > st.ring_spectra) st.in_pos = 0;
-    if (st.out_pos + S > st.ring_spectra) st.out_pos = 0;
     ppf_chunk c;
-    c.in = st.in + st.in_pos * st.N;
-    c.out = st.out + st.out_pos * st.N;
     c.nspectra = S;
     c.tag = (unsigned long long)submitted;
-    st.in_pos += S;
-    st.out_pos += S;
+    if (st.chk_in && !st.chk_done && st.chk_pos + S <= st.chk_spectra) {
+      c.in = st.chk_in + st.chk_pos * st.N;
+      c.out = st.chk_out + st.chk_pos * st.N;
+      st.chk_pos += S;
+    } else {
+      // a checked stream whose input is used up stays on the ring from here
+      st.chk_done = true;
+      if (st.in_pos + S > st.ring_spectra) st.in_pos = 0;
+      if (st.out_pos + S > st.ring_spectra) st.out_pos = 0;
+      c.in = st.in + st.in_pos * st.N;
+      c.out = st.out + st.out_pos * st.N;
+      st.in_pos += S;
+      st.out_pos += S;
+    }
     long long now = ppf_clock_ns();
     while (now < ta) now = ppf_clock_ns();
     if (now - ta > 20000) late++;
-    PK(ppf_server_submit(srv, st.id, &c, ta));
+    PK(ppf_server_submit(st.h, &c, ta));
     submitted++;
   }
   const int drain_status = ppf_server_drain(srv, 60.0);
   stop_poll = true;
   poller.join();
-  ppf_server_stats s;
+  ppf_server_stats_t s;
   PK(ppf_server_get_stats(srv, &s));
+  long long checked_chunks_spectra = 0;
+  for (auto& kv : checked) {
+    Stream& st = streams[kv.first];
+    const size_t bytes = (size_t)st.chk_pos * st.N * sizeof(float2);
+    std::vector<float2> host((size_t)st.chk_pos * st.N);
+    if (bytes) CK(hipMemcpy(host.data(), st.chk_out, bytes, hipMemcpyDeviceToHost));
+    const std::string of = check_dir + "/out_" + std::to_string(kv.first) + ".c64";
+    FILE* f = fopen(of.c_str(), "wb");
+    if (!f || fwrite(host.data(), 1, bytes, f) != bytes) {
+      fprintf(stderr, "cannot write %s\n", of.c_str());
+      return 5;
+    }
+    fclose(f);
+    std::ofstream(check_dir + "/out_" + std::to_string(kv.first) + ".txt") << st.chk_pos << "\n";
+    checked_chunks_spectra += st.chk_pos;
+  }
   const double offered = load * 6.5;
   printf("{\"workload\": \"serve_%dstreams_load%g\", \"load_multiple\": %g, \"offered_gbps\": %.2f, "
          "\"sustained_gbps\": %.2f, \"realtime_multiple\": %.2f, \"p50_us\": %.1f, \"p99_us\": %.1f, "
          "\"max_us\": %.1f, \"mean_us\": %.1f, \"chunks\": %lld, \"batches\": %lld, \"mean_batch_chunks\": %.1f, "
          "\"chunk_rate_per_s\": %.0f, \"streams\": %d, \"mean_n\": %.1f, \"seconds\": %g, \"late_submits\": %lld, "
          "\"drain_status\": %d, \"state_bytes_used\": %lld, \"mean_batch_gpu_us\": %.1f, \"mean_form_us\": %.1f, "
-         "\"mean_launch_us\": %.1f}\n",
+         "\"mean_launch_us\": %.1f, \"checked_spectra\": %lld, \"tags_dropped\": %lld}\n",
          nstreams, load, load, offered, s.input_gbps, s.input_gbps / 6.5, s.p50_us, s.p99_us, s.max_us,
          s.mean_us, s.chunks_done, s.batches, s.mean_batch_chunks, s.elapsed_s > 0 ? s.chunks_done / s.elapsed_s : 0.0,
          nstreams, mean_n, seconds, late, drain_status, s.state_bytes_used, s.mean_batch_gpu_us, s.mean_form_us,
-         s.mean_launch_us);
+         s.mean_launch_us, checked_chunks_spectra, s.tags_dropped);
   fflush(stdout);
-  for (auto& st : streams) PK(ppf_server_close_stream(srv, st.id));
+  for (auto& st : streams) PK(ppf_stream_destroy(st.h));
   PK(ppf_server_destroy(srv));
   for (auto& st : streams) {
     CK(hipFree(st.in));
     CK(hipFree(st.out));
+    if (st.chk_in) CK(hipFree(st.chk_in));
+    if (st.chk_out) CK(hipFree(st.chk_out));
   }
   for (auto& kv : plans) ppf_destroy(kv.second);
   return drain_status == PPF_OK ? 0 : 4;

@@ -51,9 +51,13 @@ class ppf_chunk(ctypes.Structure):  # noqa: N801 - the C name
     _fields_ = [("in_", _c_vp), ("out", _c_vp), ("nspectra", _c_ll), ("tag", ctypes.c_ulonglong)]
 
 
-class ppf_server_stats(ctypes.Structure):  # noqa: N801 - the C name
+# flags of ppf_server_open_stream_ex
+PPF_OPEN_QUEUE, PPF_OPEN_NOWAIT = 0, 1
+
+
+class ppf_server_stats_t(ctypes.Structure):  # noqa: N801 - the C name
     _fields_ = [(n, _c_ll) for n in ("chunks_done", "spectra_done", "bytes_in_done", "batches", "admitted",
-                                     "rejected", "queued_admissions", "state_bytes_used")] + \
+                                     "rejected", "queued_admissions", "state_bytes_used", "tags_dropped")] + \
                [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "max_us", "mean_us", "elapsed_s",
                                                "input_gbps", "mean_batch_chunks", "mean_batch_gpu_us",
                                                "mean_form_us", "mean_launch_us")]
@@ -86,12 +90,15 @@ _SIGNATURES = [
     ("ppf_stream_destroy", _c_int, [_c_vp]),
     ("ppf_clock_ns", _c_ll, []),
     ("ppf_server_create", _c_vp, [ctypes.c_size_t, _c_int]),
-    ("ppf_server_open_stream", _c_int, [_c_vp, _c_vp, _c_int, ctypes.POINTER(_c_int)]),
-    ("ppf_server_stream_admitted", _c_int, [_c_vp, _c_int]),
-    ("ppf_server_submit", _c_int, [_c_vp, _c_int, _c_vp, _c_ll]),
+    ("ppf_server_open_stream", _c_int, [_c_vp, _c_vp, ctypes.POINTER(_c_vp)]),
+    ("ppf_server_open_stream_ex", _c_int, [_c_vp, _c_vp, _c_int, ctypes.POINTER(_c_vp)]),
+    ("ppf_server_stream_admitted", _c_int, [_c_vp]),
+    ("ppf_server_submit", _c_int, [_c_vp, _c_vp, _c_ll]),
     ("ppf_server_poll", _c_int, [_c_vp, ctypes.POINTER(ctypes.c_ulonglong), _c_int]),
     ("ppf_server_drain", _c_int, [_c_vp, ctypes.c_double]),
-    ("ppf_server_close_stream", _c_int, [_c_vp, _c_int]),
+    ("ppf_server_close_stream", _c_int, [_c_vp]),
+    ("ppf_server_stats", _c_int, [_c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
     ("ppf_server_get_stats", _c_int, [_c_vp, _c_vp]),
     ("ppf_server_reset_stats", _c_int, [_c_vp]),
     ("ppf_server_destroy", _c_int, [_c_vp]),
@@ -274,23 +281,29 @@ def ppf_server_create(hbm_budget_bytes: int, max_inflight: int = 2) -> int:
     return _handle(lib().ppf_server_create(int(hbm_budget_bytes), int(max_inflight)))
 
 
-def ppf_server_open_stream(server: int, plan: int, wait_for_budget: bool = False) -> int:
-    sid = _c_int(-1)
-    _check(lib().ppf_server_open_stream(server, plan, int(bool(wait_for_budget)), ctypes.byref(sid)))
-    return int(sid.value)
+def ppf_server_open_stream(server: int, plan: int) -> int:
+    """A server stream handle (waits in line for budget if needed)."""
+    h = _c_vp()
+    _check(lib().ppf_server_open_stream(server, plan, ctypes.byref(h)))
+    return int(h.value)
 
 
-def ppf_server_stream_admitted(server: int, stream_id: int) -> bool:
-    r = int(lib().ppf_server_stream_admitted(server, int(stream_id)))
+def ppf_server_open_stream_ex(server: int, plan: int, flags: int) -> int:
+    h = _c_vp()
+    _check(lib().ppf_server_open_stream_ex(server, plan, int(flags), ctypes.byref(h)))
+    return int(h.value)
+
+
+def ppf_server_stream_admitted(stream: int) -> bool:
+    r = int(lib().ppf_server_stream_admitted(stream))
     if r < 0:
         _check(r)
     return r == 1
 
 
-def ppf_server_submit(server: int, stream_id: int, inp, out, nspectra: int, tag: int = 0,
-                      arrival_ns: int = -1) -> int:
+def ppf_server_submit(stream: int, inp, out, nspectra: int, tag: int = 0, arrival_ns: int = -1) -> int:
     ch = ppf_chunk(_addr(inp), _addr(out), int(nspectra), int(tag))
-    return _check(lib().ppf_server_submit(server, int(stream_id), ctypes.byref(ch), int(arrival_ns)))
+    return _check(lib().ppf_server_submit(stream, ctypes.byref(ch), int(arrival_ns)))
 
 
 def ppf_server_poll(server: int, max_tags: int = 4096) -> list[int]:
@@ -305,14 +318,21 @@ def ppf_server_drain(server: int, timeout_s: float = 60.0) -> int:
     return _check(lib().ppf_server_drain(server, float(timeout_s)))
 
 
-def ppf_server_close_stream(server: int, stream_id: int) -> int:
-    return _check(lib().ppf_server_close_stream(server, int(stream_id)))
+def ppf_server_close_stream(stream: int) -> int:
+    return _check(lib().ppf_server_close_stream(stream))
+
+
+def ppf_server_stats(server: int) -> tuple[float, float, float]:
+    """(p50 us, p99 us, input GB/s) of the chunks since the last reset."""
+    p50, p99, gbps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().ppf_server_stats(server, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(gbps)))
+    return float(p50.value), float(p99.value), float(gbps.value)
 
 
 def ppf_server_get_stats(server: int) -> dict:
-    st = ppf_server_stats()
+    st = ppf_server_stats_t()
     _check(lib().ppf_server_get_stats(server, ctypes.byref(st)))
-    return {name: getattr(st, name) for name, _ in ppf_server_stats._fields_}
+    return {name: getattr(st, name) for name, _ in ppf_server_stats_t._fields_}
 
 
 def ppf_server_reset_stats(server: int) -> int:

@@ -119,3 +119,21 @@ def test_error_raises_in_binding():
     with pytest.raises(ppf.PPFError) as ei:
         ppf.ppf_plan(100, 8, np.ones(800, np.float32))
     assert ei.value.status == ppf.PPF_ERR_UNSUPPORTED
+
+
+def test_server_entry_points_reject_null_handles():
+    L = ppf.lib()
+    p50, p99, gb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    assert L.ppf_server_stats(None, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(gb)) == ppf.PPF_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert L.ppf_server_open_stream(None, None, ctypes.byref(h)) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_open_stream_ex(None, None, ppf.PPF_OPEN_NOWAIT, ctypes.byref(h)) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_submit(None, None, -1) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_stream_admitted(None) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_close_stream(None) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_poll(None, None, 0) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_drain(None, 1.0) == ppf.PPF_ERR_INVALID
+    assert L.ppf_server_destroy(None) == ppf.PPF_OK
+    assert L.ppf_stream_push(None, None) == ppf.PPF_ERR_INVALID
+    assert L.ppf_stream_destroy(None) == ppf.PPF_OK
+    assert L.ppf_execute_power(None, None, None, 16, 4) == ppf.PPF_ERR_INVALID

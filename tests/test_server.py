@@ -52,14 +52,14 @@ class Workload:
             self.coeffs[(n, taps)] = rng2.standard_normal(taps * n).astype(np.float32)
 
     def run(self, server, plans, which, order_seed):
-        """Submit the chunks of streams `which`, interleaved across streams in a
+        """Push the chunks of streams `which`, interleaved across streams in a
         random order (in order within a stream); return outputs per stream."""
         torch = self.torch
-        ids = {}
+        handles = {}
         outs = {}
         for k in which:
             st = self.streams[k]
-            ids[k] = ppf.ppf_server_open_stream(server, plans[(st["n"], st["taps"])].handle)
+            handles[k] = ppf.ppf_server_open_stream(server, plans[(st["n"], st["taps"])].handle)
             outs[k] = [torch.full((s, st["n"]), float("nan"), dtype=torch.complex64, device="cuda")
                        for s in st["lens"]]
         cursor = {k: 0 for k in which}
@@ -71,7 +71,7 @@ class Workload:
             i = cursor[k]
             st = self.streams[k]
             tag = k * 1000 + i
-            ppf.ppf_server_submit(server, ids[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=tag)
+            ppf.ppf_stream_push(handles[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=tag)
             tags.append(tag)
             cursor[k] += 1
             if cursor[k] == len(st["lens"]):
@@ -85,7 +85,7 @@ class Workload:
             done.extend(got)
         assert sorted(done) == sorted(tags)
         for k in which:
-            ppf.ppf_server_close_stream(server, ids[k])
+            ppf.ppf_stream_destroy(handles[k])
         torch.cuda.synchronize()
         return {k: np.concatenate([o.cpu().numpy() for o in outs[k]]) for k in which}
 
@@ -95,6 +95,9 @@ def _plans(coeffs):
 
 
 def test_mix_matches_oracle_and_alone():
+    """Twelve streams of four plans pushed interleaved through one server
+    match the oracle's stream form, and every stream, run alone in a fresh
+    server, gives bit-identical spectra to its spectra in the mix."""
     torch = _torch()
     wl = Workload(torch, n_streams=12, seed=5)
     plans = _plans(wl.coeffs)
@@ -102,10 +105,12 @@ def test_mix_matches_oracle_and_alone():
     try:
         mix = wl.run(srv, plans, list(range(12)), order_seed=1)
         stats = ppf.ppf_server_get_stats(srv)
+        p50, p99, gbps = ppf.ppf_server_stats(srv)
     finally:
         ppf.ppf_server_destroy(srv)
     assert stats["chunks_done"] == sum(len(s["lens"]) for s in wl.streams)
     assert stats["batches"] >= 1 and stats["p99_us"] >= stats["p50_us"] > 0
+    assert (p50, p99) == (stats["p50_us"], stats["p99_us"]) and gbps > 0
     for k, st in enumerate(wl.streams):
         h = wl.coeffs[(st["n"], st["taps"])]
         ref = np.concatenate(oracle.ppf_stream(st["chunks"], h, st["n"], st["taps"]))
@@ -113,16 +118,22 @@ def test_mix_matches_oracle_and_alone():
         err = rel_err(mix[k], ref)
         print(f"stream {k} N={st['n']} T={st['taps']} chunks={st['lens']} err={err:.2e}")
         assert err <= TOL, (k, err)
-    # stream 0 alone in a fresh server: same spectra
-    srv = ppf.ppf_server_create(1 << 32, 2)
-    try:
-        alone = wl.run(srv, plans, [0], order_seed=2)
-    finally:
-        ppf.ppf_server_destroy(srv)
-    assert rel_err(alone[0], mix[0].astype(np.complex128)) <= TOL
-    assert np.array_equal(alone[0], mix[0])
+    for k in range(12):
+        srv = ppf.ppf_server_create(1 << 32, 2)
+        try:
+            alone = wl.run(srv, plans, [k], order_seed=2 + k)
+        finally:
+            ppf.ppf_server_destroy(srv)
+        assert np.array_equal(alone[k], mix[k]), k
     for p in plans.values():
         p.close()
+
+
+def _fixed_bytes():
+    probe = ppf.ppf_server_create(1 << 32, 2)
+    fixed = ppf.ppf_server_get_stats(probe)["state_bytes_used"]   # the server's own buffers
+    ppf.ppf_server_destroy(probe)
+    return fixed
 
 
 def test_budget_admission_queues_and_releases():
@@ -130,61 +141,179 @@ def test_budget_admission_queues_and_releases():
     wl = Workload(torch, n_streams=1, seed=9, chunks_per_stream=1)
     plans = _plans(wl.coeffs)
     state = 2 * (8 - 1) * 1024 * 8 + 4096          # two history buffers + bookkeeping
-    probe = ppf.ppf_server_create(1 << 32, 2)
-    fixed = ppf.ppf_server_get_stats(probe)["state_bytes_used"]   # the server's own buffers
-    ppf.ppf_server_destroy(probe)
-    srv = ppf.ppf_server_create(fixed + 2 * state + 100, 2)
+    srv = ppf.ppf_server_create(_fixed_bytes() + 2 * state + 100, 2)
     try:
         key = (1024, 8)
         a = ppf.ppf_server_open_stream(srv, plans[key].handle)
         b = ppf.ppf_server_open_stream(srv, plans[key].handle)
         with pytest.raises(ppf.PPFError) as ei:
-            ppf.ppf_server_open_stream(srv, plans[key].handle, wait_for_budget=False)
+            ppf.ppf_server_open_stream_ex(srv, plans[key].handle, ppf.PPF_OPEN_NOWAIT)
         assert ei.value.status == ppf.PPF_ERR_BUDGET
-        c = ppf.ppf_server_open_stream(srv, plans[key].handle, wait_for_budget=True)
-        assert not ppf.ppf_server_stream_admitted(srv, c)
+        c = ppf.ppf_server_open_stream(srv, plans[key].handle)     # waits in line
+        assert not ppf.ppf_server_stream_admitted(c)
         x = signals.complex_gaussian(20 * 1024, 1.0, seed=77)
         xd = torch.from_numpy(x).cuda()
         od = torch.empty((20, 1024), dtype=torch.complex64, device="cuda")
-        ppf.ppf_server_submit(srv, c, xd, od, 20, tag=7)     # waits with the stream
-        ppf.ppf_server_close_stream(srv, a)                   # frees budget: c is admitted
+        ppf.ppf_server_submit(c, xd, od, 20, tag=7)      # waits with the stream
+        ppf.ppf_stream_destroy(a)                         # frees budget: c is admitted
         ppf.ppf_server_drain(srv, 60.0)
-        assert ppf.ppf_server_stream_admitted(srv, c)
+        assert ppf.ppf_server_stream_admitted(c)
         assert ppf.ppf_server_poll(srv) == [7]
         ref = oracle.ppf_stream([x], wl.coeffs[key], 1024, 8)[0]
         assert rel_err(od.cpu().numpy(), ref) <= TOL
         stats = ppf.ppf_server_get_stats(srv)
         assert stats["rejected"] == 1 and stats["queued_admissions"] == 1
-        ppf.ppf_server_close_stream(srv, b)
-        ppf.ppf_server_close_stream(srv, c)
+        ppf.ppf_stream_destroy(b)
+        ppf.ppf_stream_destroy(c)
     finally:
         ppf.ppf_server_destroy(srv)
     for p in plans.values():
         p.close()
 
 
+def test_state_that_can_never_fit_is_refused():
+    _torch()
+    plan = ppf.Plan(16384, 64, np.ones(16384 * 64, np.float32))
+    srv = ppf.ppf_server_create(_fixed_bytes() + 1000, 2)
+    try:
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_server_open_stream(srv, plan.handle)
+        assert ei.value.status == ppf.PPF_ERR_BUDGET
+    finally:
+        ppf.ppf_server_destroy(srv)
+    plan.close()
+
+
+def test_close_while_waiting_drops_its_chunks():
+    """A stream closed before admission leaves the line; its pushed chunks
+    are dropped, so drain and destroy still return."""
+    torch = _torch()
+    plan = ppf.Plan(1024, 8, np.ones(8192, np.float32))
+    state = 2 * 7 * 1024 * 8 + 4096
+    srv = ppf.ppf_server_create(_fixed_bytes() + state + 100, 2)
+    try:
+        a = ppf.ppf_server_open_stream(srv, plan.handle)
+        c = ppf.ppf_server_open_stream(srv, plan.handle)           # waits
+        assert not ppf.ppf_server_stream_admitted(c)
+        xd = torch.zeros(4 * 1024, dtype=torch.complex64, device="cuda")
+        od = torch.empty_like(xd)
+        for i in range(3):
+            ppf.ppf_stream_push(c, xd, od, 4, tag=100 + i)
+        ppf.ppf_server_close_stream(c)
+        with pytest.raises(ppf.PPFError):
+            ppf.ppf_stream_push(c, xd, od, 4)                       # closed
+        assert ppf.ppf_server_drain(srv, 10.0) == ppf.PPF_OK
+        assert ppf.ppf_server_poll(srv) == []                        # dropped, never reported
+        ppf.ppf_stream_destroy(c)
+        ppf.ppf_stream_destroy(a)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    plan.close()
+
+
+def test_close_admits_waiting_stream_while_batches_run():
+    """The budget of a closed stream is given back as soon as its own chunks
+    are done, not when the GPU next goes idle: a waiting stream is admitted
+    while another stream's batches are still running."""
+    torch = _torch()
+    plan = ppf.Plan(1024, 8, np.ones(8192, np.float32))
+    state = 2 * 7 * 1024 * 8 + 4096
+    srv = ppf.ppf_server_create(_fixed_bytes() + 2 * state + 100, 2)
+    try:
+        busy = ppf.ppf_server_open_stream(srv, plan.handle)
+        a = ppf.ppf_server_open_stream(srv, plan.handle)
+        c = ppf.ppf_server_open_stream(srv, plan.handle)            # waits
+        assert not ppf.ppf_server_stream_admitted(c)
+        spectra = 8192
+        xd = torch.zeros(spectra * 1024, dtype=torch.complex64, device="cuda")
+        od = torch.empty_like(xd)
+        n_busy = 1500
+        for i in range(n_busy):
+            ppf.ppf_stream_push(busy, xd, od, spectra, tag=i)
+        ppf.ppf_server_close_stream(a)
+        import time
+        t_end = time.time() + 10.0
+        while not ppf.ppf_server_stream_admitted(c) and time.time() < t_end:
+            time.sleep(0.0002)
+        done_at_admission = len(ppf.ppf_server_poll(srv, 1 << 16))
+        assert ppf.ppf_server_stream_admitted(c)
+        print(f"waiting stream admitted after {done_at_admission} of {n_busy} busy chunks", flush=True)
+        assert done_at_admission < n_busy
+        ppf.ppf_server_drain(srv, 120.0)
+        for h in (busy, a, c):
+            ppf.ppf_stream_destroy(h)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    plan.close()
+
+
+def test_chunk_larger_than_a_batch_runs_in_pieces():
+    """A chunk beyond what one batch holds (N=4096, T=16 two-pass: 16384
+    spectra fill the 512 MiB workspace) runs as consecutive pieces and
+    reports its tag once; its spectra on both sides of the piece boundary
+    and along the chunk match the oracle."""
+    torch = _torch()
+    n, taps = 4096, 16
+    h = np.random.default_rng(31).standard_normal(taps * n).astype(np.float32)
+    plan = ppf.Plan(n, taps, h)
+    assert plan.path == ppf.PPF_PATH_TWO_PASS
+    s_chunk = 16384 + 100
+    x = signals.complex_gaussian(s_chunk * n, 1.0, seed=4242)
+    xd = torch.from_numpy(x).cuda()
+    od = torch.full((s_chunk, n), float("nan"), dtype=torch.complex64, device="cuda")
+    srv = ppf.ppf_server_create(4 << 30, 2)
+    try:
+        st = ppf.ppf_server_open_stream(srv, plan.handle)
+        ppf.ppf_stream_push(st, xd, od, s_chunk, tag=99)
+        ppf.ppf_server_drain(srv, 120.0)
+        assert ppf.ppf_server_poll(srv) == [99]
+        ppf.ppf_stream_destroy(st)
+    finally:
+        ppf.ppf_server_destroy(srv)
+    got = od.cpu().numpy()
+    assert np.isfinite(got).all()
+    whole = np.concatenate([np.zeros((taps - 1) * n, np.complex64), x])
+    idx = sorted(set(list(range(0, s_chunk, 97)) + list(range(16384 - 20, 16384 + 20)) +
+                     list(range(taps)) + [s_chunk - 1]))
+    ref = oracle.ppf(whole, h, n, taps, spectra=idx)
+    err = rel_err(got[idx], ref)
+    print(f"N={n} T={taps} chunk of {s_chunk} spectra in pieces: max err / rms = {err:.3e}")
+    assert err <= TOL
+    plan.close()
+
+
 def test_submit_errors():
     torch = _torch()
     plan = ppf.Plan(256, 4, np.ones(1024, np.float32))
     srv = ppf.ppf_server_create(1 << 30, 1)
+    plain = ppf.ppf_stream_create(plan.handle)
     try:
         sid = ppf.ppf_server_open_stream(srv, plan.handle)
         buf = torch.zeros(8 * 256, dtype=torch.complex64, device="cuda")
         out = torch.empty_like(buf)
         with pytest.raises(ppf.PPFError) as ei:
-            ppf.ppf_server_submit(srv, sid + 100, buf, out, 2)
+            ppf.ppf_server_submit(plain, buf, out, 2)          # not a server stream
         assert ei.value.status == ppf.PPF_ERR_INVALID
         with pytest.raises(ppf.PPFError) as ei:
-            ppf.ppf_server_submit(srv, sid, buf, out, 0)
+            ppf.ppf_server_submit(sid, buf, out, -1)
         assert ei.value.status == ppf.PPF_ERR_INVALID
         with pytest.raises(ppf.PPFError) as ei:
-            ppf.ppf_server_submit(srv, sid, buf.data_ptr() + 8, out, 2)
+            ppf.ppf_server_submit(sid, buf.data_ptr() + 8, out, 2)
         assert ei.value.status == ppf.PPF_ERR_ALIGN
-        ppf.ppf_server_close_stream(srv, sid)
+        with pytest.raises(ppf.PPFError) as ei:
+            ppf.ppf_stream_get_history(sid, np.zeros(3 * 256, np.complex64))
+        assert ei.value.status == ppf.PPF_ERR_UNSUPPORTED
+        assert ppf.ppf_stream_position(sid) == 0
+        ppf.ppf_stream_push(sid, buf, out, 2, tag=5)
+        assert ppf.ppf_stream_position(sid) == 2
+        ppf.ppf_server_drain(srv, 10.0)
+        ppf.ppf_server_close_stream(sid)
         with pytest.raises(ppf.PPFError):
-            ppf.ppf_server_submit(srv, sid, buf, out, 2)
+            ppf.ppf_server_submit(sid, buf, out, 2)
+        ppf.ppf_stream_destroy(sid)
     finally:
         ppf.ppf_server_destroy(srv)
+        ppf.ppf_stream_destroy(plain)
     with pytest.raises(ppf.PPFError) as ei:
         ppf.ppf_server_create(1 << 20, 2)
     assert ei.value.status == ppf.PPF_ERR_BUDGET
@@ -220,7 +349,7 @@ def test_runs_of_short_chunks_match_oracle():
         for i in range(max(len(s[2]) for s in streams)):
             for k, (n, taps, lens, chunks) in enumerate(streams):
                 if i < len(lens):
-                    ppf.ppf_server_submit(srv, ids[k], keep[k][i], outs[k][i], lens[i], tag=k * 100 + i)
+                    ppf.ppf_server_submit(ids[k], keep[k][i], outs[k][i], lens[i], tag=k * 100 + i)
         ppf.ppf_server_drain(srv, 120.0)
         for k, (n, taps, lens, chunks) in enumerate(streams):
             got = np.concatenate([o.cpu().numpy() for o in outs[k]])
@@ -228,7 +357,7 @@ def test_runs_of_short_chunks_match_oracle():
             err = rel_err(got, ref)
             print(f"short-chunk stream N={n} T={taps} err={err:.2e}")
             assert err <= TOL, (n, taps, err)
-            ppf.ppf_server_close_stream(srv, ids[k])
+            ppf.ppf_stream_destroy(ids[k])
     finally:
         ppf.ppf_server_destroy(srv)
     for p, _ in plans.values():
@@ -274,13 +403,13 @@ def test_c5_mix_sampled_streams():
             k = live[int(rng.integers(len(live)))]
             i = cursor[k]
             st = streams[k]
-            ppf.ppf_server_submit(srv, ids[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=k * 1000 + i)
+            ppf.ppf_server_submit(ids[k], st["dev_in"][i], outs[k][i], st["lens"][i], tag=k * 1000 + i)
             cursor[k] += 1
             if cursor[k] == chunks_per_stream:
                 live.remove(k)
         ppf.ppf_server_drain(srv, 120.0)
         for k in range(n_streams):
-            ppf.ppf_server_close_stream(srv, ids[k])
+            ppf.ppf_stream_destroy(ids[k])
         torch.cuda.synchronize()
     finally:
         ppf.ppf_server_destroy(srv)
