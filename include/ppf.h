@@ -207,6 +207,24 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
  */
 int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K);
 
+/*
+ * ppf_execute_noalloc - ppf_execute that allocates nothing, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid it).
+ *
+ * Same arguments, stream, layout and errors as ppf_execute. The two-pass
+ * path presums into a static device workspace of PPF_NOALLOC_SCRATCH_BYTES
+ * (32 MiB, one per GPU, held until the process ends) instead of the
+ * per-stream workspace ppf_execute allocates: a two-pass batch whose
+ * presums (nspectra * N * 8 bytes) exceed it is PPF_ERR_UNSUPPORTED, with
+ * nothing launched (split the batch). Fused and matrix-core plans use no
+ * workspace and take any nspectra. Every call on a GPU shares that GPU's
+ * workspace: two-pass calls that overlap on one GPU (different streams or
+ * threads) race and must be ordered by the caller.
+ */
+#define PPF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int ppf_execute_noalloc(ppf_plan_t plan, const void* in, void* out, long long nspectra);
+
 /* ppf_destroy - wait for every HIP stream the plan has run on, then free the
  * plan. No other call may use the plan meanwhile. NULL is a no-op. */
 int ppf_destroy(ppf_plan_t plan);

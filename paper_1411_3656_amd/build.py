@@ -24,7 +24,8 @@ CSRC = PKG / "csrc"
 BUILD = ROOT / "_build"
 LIB = PKG / "libppf.so"
 
-SOURCES = ["ppf_kernels.hip", "ppf_power.hip", "ppf_mfma.hip", "ppf_design.hip", "ppf_api.cpp", "ppf_server.cpp"]
+SOURCES = ["ppf_kernels.hip", "ppf_power.hip", "ppf_mfma.hip", "ppf_design.hip", "ppf_api.cpp", "ppf_server.cpp",
+           "ppf_noalloc.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -254,8 +254,10 @@ int ensure_workspace(ppf_plan_t p, hipStream_t st, long long min_spectra, void**
 }
 
 // FIR + FFT over M spectra of the concatenation x0 (h0 blocks) ++ x1.
+// ext_ws: a caller-provided workspace of ext_spectra spectra for the
+// two-pass path (nothing is allocated then), or NULL for the stream's own.
 int run_batch(ppf_plan_t p, hipStream_t stream, const void* x0, long long h0, const void* x1, void* out,
-              long long M) {
+              long long M, void* ext_ws = nullptr, long long ext_spectra = 0) {
   const ppf::PlanDev pd = p->dev();
   const size_t sb = (size_t)sample_bytes(p->in_type);
   if (p->fft_mode == PPF_FFT_MFMA_F16) {
@@ -272,8 +274,13 @@ int run_batch(ppf_plan_t p, hipStream_t stream, const void* x0, long long h0, co
   }
   void* ws = nullptr;
   long long chunk = 0;
-  int st = ensure_workspace(p, stream, 1, &ws, &chunk);
-  if (st != PPF_OK) return st;
+  if (ext_ws) {
+    ws = ext_ws;
+    chunk = ext_spectra;
+  } else {
+    int st = ensure_workspace(p, stream, 1, &ws, &chunk);
+    if (st != PPF_OK) return st;
+  }
   for (long long c0 = 0; c0 < M; c0 += chunk) {
     const long long k = (M - c0 < chunk) ? (M - c0) : chunk;
     // blocks c0 .. of the concatenation: split between x0 and x1
@@ -489,6 +496,33 @@ hip_fail:
 }  // namespace
 
 ppf::PlanDev ppf_internal_plan_dev(const ppf_plan_s* plan) { return plan->dev(); }
+
+int ppf_internal_execute_in(ppf_plan_s* plan, const void* in, void* out, long long nspectra, void* ws,
+                            size_t ws_bytes) {
+  try {
+    if (!plan) return fail(PPF_ERR_INVALID, "plan is NULL");
+    if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
+    if (nspectra == 0) { g_status = PPF_OK; return PPF_OK; }
+    if (!in || !out) return fail(PPF_ERR_INVALID, "in or out is NULL");
+    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return fail(PPF_ERR_ALIGN, "in and out must be 16-byte aligned");
+    const size_t sb = (size_t)sample_bytes(plan->in_type);
+    const size_t in_bytes = (size_t)(nspectra + plan->T - 1) * plan->N * sb;
+    const size_t out_bytes = (size_t)nspectra * plan->N * 8;
+    if (overlaps((uintptr_t)in, in_bytes, (uintptr_t)out, out_bytes)) return fail(PPF_ERR_INVALID, "in and out overlap");
+    const bool two_pass = plan->fft_mode != PPF_FFT_MFMA_F16 && plan->path == PPF_PATH_TWO_PASS;
+    if (two_pass && out_bytes > ws_bytes)
+      return fail(PPF_ERR_UNSUPPORTED,
+                  "%lld spectra of N=%d need %zu bytes of workspace, above the %zu-byte static workspace: "
+                  "split the batch", nspectra, plan->N, out_bytes, ws_bytes);
+    const hipStream_t stream = plan->stream();
+    plan->note_stream(stream);   // host bookkeeping for ppf_destroy; no device memory
+    const int st = run_batch(plan, stream, in, 0, in, out, nspectra, ws, nspectra);
+    if (st == PPF_OK) g_status = PPF_OK;
+    return st;
+  } catch (...) {
+    return fail(PPF_ERR_HIP, "unexpected exception in ppf_execute_noalloc");
+  }
+}
 
 void ppf_internal_set_error(int status, const char* message) {
   g_status = status;

@@ -130,6 +130,11 @@ struct ppf_chunk;
 ppf::PlanDev ppf_internal_plan_dev(const ppf_plan_s* plan);
 // Record a failure as the calling thread's last error.
 void ppf_internal_set_error(int status, const char* message);
+// ppf_execute with the two-pass workspace given by the caller (ws_bytes
+// bytes of device memory): allocates nothing; batches whose presums exceed
+// ws_bytes are rejected (ppf_noalloc.hip).
+int ppf_internal_execute_in(ppf_plan_s* plan, const void* in, void* out, long long nspectra, void* ws,
+                            size_t ws_bytes);
 
 namespace ppf {
 struct SrvStream;   // a server's per-stream state (ppf_server.cpp)

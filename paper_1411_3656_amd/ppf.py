@@ -77,6 +77,7 @@ _SIGNATURES = [
     ("ppf_plan_set_path", _c_int, [_c_vp, _c_int]),
     ("ppf_plan_query", _c_int, [_c_vp, _c_int, ctypes.POINTER(_c_ll)]),
     ("ppf_execute", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
+    ("ppf_execute_noalloc", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll]),
     ("ppf_execute_host", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_ll]),
     ("ppf_execute_power", _c_int, [_c_vp, _c_vp, _c_vp, _c_ll, _c_int]),
     ("ppf_destroy", _c_int, [_c_vp]),
@@ -208,6 +209,13 @@ def ppf_plan_query(plan: int, key: int) -> int:
 
 def ppf_execute(plan: int, inp, out, nspectra: int) -> int:
     return _check(lib().ppf_execute(plan, _addr(inp), _addr(out), int(nspectra)))
+
+
+def ppf_execute_noalloc(plan: int, inp, out, nspectra: int) -> int:
+    return _check(lib().ppf_execute_noalloc(plan, _addr(inp), _addr(out), int(nspectra)))
+
+
+PPF_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def ppf_execute_host(plan: int, host_in, host_out, nspectra: int, chunk_spectra: int = 0) -> int:
