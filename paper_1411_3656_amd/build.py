@@ -79,7 +79,23 @@ def build(jobs: int = 4, verbose: bool = False, defines=(), out: pathlib.Path | 
         print(f"built {lib}", flush=True)
     if out is None:
         build_serve_bench(lib, verbose)
+        build_copy_bench(verbose)
     return lib
+
+
+def build_copy_bench(verbose: bool = False) -> pathlib.Path:
+    """The copy yardstick of the HBM roofline (no library needed)."""
+    exe = PKG / "ppf_copy_bench"
+    tmp = exe.with_suffix(".tmp")
+    cmd = [hipcc(), *COMMON, "-x", "hip", str(CSRC / "copy_bench.cpp"), "-o", str(tmp)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("build of ppf_copy_bench failed")
+    os.replace(tmp, exe)
+    if verbose:
+        print(f"built {exe}", flush=True)
+    return exe
 
 
 def build_serve_bench(lib: pathlib.Path, verbose: bool = False) -> pathlib.Path:

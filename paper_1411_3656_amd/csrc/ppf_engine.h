@@ -191,6 +191,27 @@ __device__ __forceinline__ int lds_index(int i) {
     return i + (i >> 5);
   }
 }
+// Interleaved exchange layout (N in 256..PPF_LDS_B64_MAX_N): each element
+// is one (re, im) pair, so an exchange moves 8 bytes per lane and
+// instruction (ds_write_b64 / ds_read_b64, measured 1.35x / 1.7x the bytes
+// per clock of 4-byte accesses on gfx950). Element i is stored at
+// i ^ f(i >> 5), f linear over GF(2) on the four low bits of the 32-element
+// row; the masks were found by enumerating every stage's reads and writes
+// of every configuration with N >= 256 (radix 4, 8 and 16 Stockham stages,
+// 1..4 groups per block): within each half-wave of 32 lanes the 8-byte
+// slots are then distinct modulo 32, i.e. no bank conflicts.
+#ifndef PPF_LDS_B64
+#define PPF_LDS_B64 1
+#endif
+#ifndef PPF_LDS_B64_MAX_N
+#define PPF_LDS_B64_MAX_N 16384
+#endif
+constexpr bool lds_b64(int N) { return PPF_LDS_B64 && N >= 256 && N <= PPF_LDS_B64_MAX_N; }
+__device__ __forceinline__ int swz64(int i) {
+  const int r = i >> 5;
+  return i ^ ((r & 1 ? 22 : 0) ^ (r & 2 ? 29 : 0) ^ (r & 4 ? 12 : 0) ^ (r & 8 ? 18 : 0));
+}
+
 constexpr int plane_floats(int N, int W) {
   if (N >= 8192) return N;
   if (N >= 256) return N;
@@ -218,15 +239,30 @@ struct GroupFft {
   // stage S reads its twiddles from the table when it starts
   static constexpr bool tw_fetched(int S) { return TWG && S > 0 && (!TWR || ns_at(N, RX, S) > W); }
   static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
+  static constexpr bool IL = lds_b64(N);             // interleaved (re, im) elements
+  // XL (large N, 16 or 32 elements per thread): swz64 is linear, changes
+  // only bits 0-4 and depends only on bits 5-8, and a Stockham stage's
+  // element index is the thread's base with the q digit (and the
+  // butterfly's offset) in bits of their own; so an element's address is
+  // one base per stage XORed with swz64 of its offset, which is a plain
+  // add for offsets that are multiples of 512. One base register per stage
+  // instead of one per element keeps the register file for the elements.
+  static constexpr bool XL = IL && N >= 8192 && W == 512;
 
   float* lds;      // shared memory base of the block
   int grp, j;
   int par;         // buffer of the next exchange (double-buffered mode)
   const v2f* tw;   // twiddle table (global)
   v2f twr[NTW];
+  int rb;          // XL: swizzled element j (the reads of every stage add e*W)
+  int wb[L];       // XL: swizzled first write element of each stage
 
   __device__ __forceinline__ float* plane(int buf, int b, int reim) const {
     return lds + (((buf * B + b) * 2 + reim) * G + grp) * PL;
+  }
+  // IL: the plane of (re, im) elements of spectrum b
+  __device__ __forceinline__ v2f* cplane(int buf, int b) const {
+    return (v2f*)lds + ((buf * B + b) * G + grp) * PL;
   }
 
   template <int S>
@@ -250,6 +286,14 @@ struct GroupFft {
 
   __device__ __forceinline__ void init(float* smem, int grp_, int j_, const v2f* tw_) {
     lds = smem; grp = grp_; j = j_; par = 0; tw = tw_;
+    if constexpr (XL) {
+      rb = swz64(j);
+#pragma unroll
+      for (int s = 0; s < L; ++s) {
+        const int ns = ns_at(N, RX, s), r = radix_at(N, RX, s);
+        wb[s] = swz64((j / ns) * ns * r + j % ns);
+      }
+    }
     load_stage_tw<1>();
   }
 
@@ -298,13 +342,24 @@ struct GroupFft {
       const int buf = DB ? par : 0;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const float* re = plane(buf, b, 0);
-        const float* im = plane(buf, b, 1);
+        if constexpr (XL) {
+          // e*W is a multiple of 512: above the swizzle
+          const v2f* pl = cplane(buf, b);
 #pragma unroll
-        for (int e = 0; e < R; ++e) {
-          const int idx = lds_index<N>(j + e * W);
-          v[b][e].x = re[idx];
-          v[b][e].y = im[idx];
+          for (int e = 0; e < R; ++e) v[b][e] = pl[rb + e * W];
+        } else if constexpr (IL) {
+          const v2f* pl = cplane(buf, b);
+#pragma unroll
+          for (int e = 0; e < R; ++e) v[b][e] = pl[swz64(j + e * W)];
+        } else {
+          const float* re = plane(buf, b, 0);
+          const float* im = plane(buf, b, 1);
+#pragma unroll
+          for (int e = 0; e < R; ++e) {
+            const int idx = lds_index<N>(j + e * W);
+            v[b][e].x = re[idx];
+            v[b][e].y = im[idx];
+          }
         }
       }
       if constexpr (DB) par ^= 1;
@@ -332,10 +387,18 @@ struct GroupFft {
     } else {
       if constexpr (!DB) __syncthreads();   // earlier reads of the single buffer are done
       const int buf = DB ? par : 0;
+      // XL: this stage's base, opaque so that the per-element addresses are
+      // formed here rather than held in registers across the spectrum loop
+      int wbs = 0;
+      if constexpr (XL) {
+        wbs = wb[S];
+        asm volatile("" : "+v"(wbs));
+      }
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         float* re = plane(buf, b, 0);
         float* im = plane(buf, b, 1);
+        v2f* pl = cplane(buf, b);
 #pragma unroll
         for (int i = 0; i < nb; ++i) {
           v2f t[r];
@@ -346,9 +409,20 @@ struct GroupFft {
           const int base = (bf / Ns) * Ns * r + (bf % Ns);
 #pragma unroll
           for (int q = 0; q < r; ++q) {
-            const int idx = lds_index<N>(base + q * Ns);
-            re[idx] = t[q].x;
-            im[idx] = t[q].y;
+            if constexpr (XL) {
+              // butterfly i sits i*W*r (Ns <= W) or i*W (Ns > W) above
+              // butterfly 0, a multiple of 512 in both cases
+              const int di = (Ns <= W) ? i * W * r : i * W;
+              const int qo = q * Ns;
+              const int idx = ((qo & 511) == 0 ? wbs + qo : (wbs ^ swz64(qo))) + di;
+              pl[idx] = t[q];
+            } else if constexpr (IL) {
+              pl[swz64(base + q * Ns)] = t[q];
+            } else {
+              const int idx = lds_index<N>(base + q * Ns);
+              re[idx] = t[q].x;
+              im[idx] = t[q].y;
+            }
           }
         }
       }
@@ -700,8 +774,11 @@ constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : (N >= 16384
 constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
 constexpr int cfg_W(int N) { return N / cfg_R(N); }
 constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
+#ifndef PPF_PF_16K
+#define PPF_PF_16K 0
+#endif
 constexpr int cfg_PF(int N, int TP) {
-  return TP == 1 ? (N >= 16384 ? 0 : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
+  return TP == 1 ? (N >= 16384 ? PPF_PF_16K : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
                  : (N >= 2048 || (PPF_SMALL16 && TP >= 16 && N <= 256) ? 2
                                   : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
 }

@@ -35,6 +35,40 @@ def counter_kib(path, kernel_substr, counter):
     return statistics.median(vals), len(vals)
 
 
+def counter_total_kib(path, kernel_substr, counter):
+    vals = [float(r["Counter_Value"]) for r in _rows(path)
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_substr!r} in {path}")
+    return sum(vals)
+
+
+def sq_md(a):
+    """Median per dispatch of every counter in the CSVs (one pass each) for
+    the kernel, with per-unit and per-CU figures."""
+    vals = {}
+    for path in a.csv:
+        for r in _rows(path):
+            if a.kernel in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    med = {k: statistics.median(v) for k, v in vals.items()}
+    out = [f"# {a.title}", "", f"Kernel matching `{a.kernel}`; counters are per dispatch (median over the "
+           "profiled dispatches), summed over the chip.", "",
+           "Commands (run from /tmp, repository at /root/repo), one pass each:", "", "```", *a.commands, "```", "",
+           "| counter | per dispatch | per unit |" if a.units else "| counter | per dispatch |",
+           "|---|---:|---:|" if a.units else "|---|---:|"]
+    for k in sorted(med):
+        if a.units:
+            out.append(f"| {k} | {med[k]:.6g} | {med[k] / a.units:.4g} |")
+        else:
+            out.append(f"| {k} | {med[k]:.6g} |")
+    if a.units:
+        out += ["", f"Units per dispatch: {a.units:.0f} (per CU: {a.units / a.cus:.1f}, {a.cus} CUs)."]
+    if a.notes:
+        out += ["", *a.notes]
+    return "\n".join(out) + "\n"
+
+
 def kernel_stats_md(path, command):
     rows = _rows(path)
     out = ["# rocprofv3 kernel statistics", "", "Command (run from /tmp, repository at /root/repo):", "",
@@ -60,17 +94,38 @@ def main(argv=None):
     t.add_argument("--copy-kernel", default="copyBuffer")
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--commands", nargs="+", required=True)
+    t.add_argument("--batches", type=int, default=0,
+                   help="sum every kernel matching --kernel (a list, comma-separated) over this many batches")
+    q = sub.add_parser("sq")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--csv", nargs="+", required=True)
+    q.add_argument("--commands", nargs="+", required=True)
+    q.add_argument("--title", required=True)
+    q.add_argument("--units", type=float, default=0.0, help="work units (e.g. spectra) per dispatch")
+    q.add_argument("--cus", type=int, default=256)
+    q.add_argument("--out", required=True)
+    q.add_argument("--notes", nargs="*", default=[], help="lines of interpretation appended to the summary")
     a = ap.parse_args(argv)
 
     if a.cmd == "stats":
         pathlib.Path(a.out).write_text(kernel_stats_md(a.csv, a.command))
         return 0
+    if a.cmd == "sq":
+        pathlib.Path(a.out).write_text(sq_md(a))
+        return 0
 
     sys.path.insert(0, str(ROOT))
     import bench  # kernel-source hash recorded beside the counters
 
-    fetch, nf = counter_kib(a.fetch, a.kernel, "FETCH_SIZE")
-    write, nw = counter_kib(a.write, a.kernel, "WRITE_SIZE")
+    if a.batches:
+        # several kernels per batch (two-pass form): the counters of every
+        # dispatch of each kernel, summed, per batch
+        fetch = sum(counter_total_kib(a.fetch, k, "FETCH_SIZE") for k in a.kernel.split(",")) / a.batches
+        write = sum(counter_total_kib(a.write, k, "WRITE_SIZE") for k in a.kernel.split(",")) / a.batches
+        nf = nw = a.batches
+    else:
+        fetch, nf = counter_kib(a.fetch, a.kernel, "FETCH_SIZE")
+        write, nw = counter_kib(a.write, a.kernel, "WRITE_SIZE")
     cfetch, _ = counter_kib(a.copy_fetch, a.copy_kernel, "FETCH_SIZE")
     cwrite, _ = counter_kib(a.copy_write, a.copy_kernel, "WRITE_SIZE")
     f_scale = a.copy_bytes / (cfetch * 1024)
