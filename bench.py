@@ -80,6 +80,17 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, h32, budget_s: float = 12.0):
     """FP64 oracle on a bounded sample: whole spectra of the same workload."""
     import oracle
@@ -101,7 +112,8 @@ def cpu_baseline(cfg, h32, budget_s: float = 12.0):
     rate = done * spectra * n * 8 / total_s / 1e9
     return {"value": round(rate, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} x {spectra} spectra of N={n}, T={taps} ({done * spectra * n} input samples), "
-                      f"{total_s:.1f} s of FP64 numpy/BLAS"}
+                      f"{total_s:.1f} s of FP64 numpy/BLAS",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def run_point(torch, n, taps, m_total, x_dev, h32, steps, warmup, path=ppf.PPF_PATH_AUTO, windows=0,
@@ -205,6 +217,7 @@ def main() -> int:
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="c2: skip the short serving leg")
     ap.add_argument("--point", default="",
                     help="sweep: run only the point 'N,T' (e.g. 512,8)")
     ap.add_argument("--chunk-mib", type=int, default=0,
@@ -403,8 +416,18 @@ def main() -> int:
         return 0
 
     if args.workload == "copy":
-        # a plain device copy of known size: the yardstick for the HBM byte
-        # counters (FETCH_SIZE, WRITE_SIZE) and the achievable copy rate
+        # plain device copies of known size: the yardstick for the HBM byte
+        # counters (FETCH_SIZE, WRITE_SIZE) and the achievable copy rate, by
+        # the native copy program (long warm-up) and by torch
+        import subprocess
+        exe = ROOT / "paper_1411_3656_amd" / "ppf_copy_bench"
+        if exe.exists():
+            res = subprocess.run([str(exe), "--mib", "1024", "--reps", str(max(20, args.steps)), "--warmup", "300"],
+                                 capture_output=True, text=True, timeout=300)
+            sys.stdout.write(res.stdout)
+            if res.returncode != 0:
+                sys.stderr.write(res.stderr)
+                return 1
         nbytes = 1 << 30
         src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -418,7 +441,7 @@ def main() -> int:
         end.record()
         torch.cuda.synchronize()
         ms = start.elapsed_time(end) / args.steps
-        print(json.dumps({"workload": "copy_1GiB", "bytes_read": nbytes, "bytes_written": nbytes,
+        print(json.dumps({"workload": "copy_1GiB_torch", "bytes_read": nbytes, "bytes_written": nbytes,
                           "ms_per_copy": round(ms, 5), "GBps_moved": round(2 * nbytes / ms / 1e6, 1)}),
               flush=True)
         return 0
@@ -465,6 +488,19 @@ def main() -> int:
                measured_traffic(args.workload), cpu)
     if args.windows:
         rec["window_ms_per_step"] = [round(w, 5) for w in res[2]]
+    if args.workload == "c2" and not args.no_serving:
+        # the metric's p99 chunk latency: a short run of the 64-stream
+        # serving mix at 100 x the real-time rate, after the timed region
+        del x_dev
+        torch.cuda.empty_cache()
+        sv = serve(100.0, 3.0, warmup=0.5)
+        if sv.get("error"):
+            rec["serving"] = {"error": sv["error"]}
+        else:
+            rec["serving"] = {"p50_us": sv["serving"]["p50_us"], "p99_us": sv["serving"]["p99_us"],
+                              "sustained_gbps": sv["value"], "realtime_multiple": sv["realtime_multiple"],
+                              "offered_load_multiple": 100.0, "seconds": 3.0,
+                              "workload": sv["config"]["workload"], "chunks": sv["serving"]["chunks"]}
     print(json.dumps(rec), flush=True)
     return 0
 
