@@ -366,21 +366,11 @@ int class_of(ppf_server_s* s, ppf_plan_t plan) {
   return (int)s->classes.size() - 1;
 }
 
-// Capture the slot's graph for the current class set (scheduler thread, slot idle).
-int build_graph(ppf_server_s* s, Slot& sl) {
-  if (sl.exec) {
-    (void)hipGraphExecDestroy(sl.exec);
-    sl.exec = nullptr;
-  }
-  for (const ClassInfo& ci : s->classes) {
-    hipError_t pe = ppf::prepare_desc(ppf_internal_plan_dev(ci.plan), ci.fused);
-    if (pe != hipSuccess) return sfail_hip(pe, "descriptor kernel set-up");
-  }
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamBeginCapture(s->launch, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return sfail_hip(e, "graph capture begin");
-  // the descriptor upload precedes each launch (only the used bytes)
-  e = hipEventRecord(s->fork, s->launch);
+// The work of one batch in slot `sl` after its descriptor upload on
+// s->launch: a fork into one branch per plan class and one for the history
+// updates, joined back into s->launch.
+hipError_t enqueue_batch(ppf_server_s* s, Slot& sl) {
+  hipError_t e = hipEventRecord(s->fork, s->launch);
   const int nc = (int)s->classes.size();
   // history updates read only the old history and the chunks: a branch of
   // their own, beside the transforms
@@ -404,6 +394,34 @@ int build_graph(ppf_server_s* s, Slot& sl) {
     if (e == hipSuccess) e = hipEventRecord(s->join[c], b);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->launch, s->join[c], 0);
   }
+  return e;
+}
+
+// Batches replay a captured graph of enqueue_batch (one launch call) unless
+// built with PPF_SERVER_GRAPH=0, which issues the same work directly.
+#ifndef PPF_SERVER_GRAPH
+#define PPF_SERVER_GRAPH 1
+#endif
+
+// Capture the slot's graph for the current class set (scheduler thread, slot idle).
+int build_graph(ppf_server_s* s, Slot& sl) {
+  if (sl.exec) {
+    (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+  }
+  for (const ClassInfo& ci : s->classes) {
+    hipError_t pe = ppf::prepare_desc(ppf_internal_plan_dev(ci.plan), ci.fused);
+    if (pe != hipSuccess) return sfail_hip(pe, "descriptor kernel set-up");
+  }
+  if (!PPF_SERVER_GRAPH) {
+    sl.graph_classes = (int)s->classes.size();
+    return PPF_OK;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(s->launch, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return sfail_hip(e, "graph capture begin");
+  if (e == hipSuccess) e = enqueue_batch(s, sl);
+  const int nc = (int)s->classes.size();
   hipError_t e2 = hipStreamEndCapture(s->launch, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -811,7 +829,7 @@ void scheduler(ppf_server_s* s) {
           hipStream_t ls = PPF_SERVER_CONCURRENT_SLOTS ? sl.stream : s->launch;
           hipError_t e = hipEventRecord(sl.start, ls);
           if (e == hipSuccess) e = hipMemcpyAsync(sl.dev, sl.host, sl.upload_bytes, hipMemcpyHostToDevice, ls);
-          if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ls);
+          if (e == hipSuccess) e = PPF_SERVER_GRAPH ? hipGraphLaunch(sl.exec, ls) : enqueue_batch(s, sl);
           if (e == hipSuccess) e = hipEventRecord(sl.done, ls);
           const long long tf2 = now_ns();
           lk.lock();
