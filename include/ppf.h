@@ -125,7 +125,12 @@ ppf_plan_t ppf_plan(int n_channels, int taps, const float* coeffs);
  * in_type: PPF_C32, PPF_C16 or PPF_CI8. Inputs are converted to FP32 in
  *         registers; the FIR accumulates in FP32. Output is always C32.
  * fft_mode: PPF_FFT_F32 or PPF_FFT_MFMA_F16 (PPF_ERR_UNSUPPORTED where the
- *         MFMA stages are not built for N).
+ *         MFMA stages are not built for N). The matrix-core mode is built
+ *         for N = 4096 = 16^3, T <= 16, PPF_R16 coefficients and PPF_CI8 or
+ *         PPF_C16 input; the samples enter the FP16 stages scaled by a power
+ *         of two chosen so that no stage input can overflow for any input
+ *         value of that type (|x| <= 128 for int8, 65504 for FP16). Any
+ *         other combination is PPF_ERR_UNSUPPORTED.
  */
 ppf_plan_t ppf_plan_ex(int n_channels, int taps, const void* coeffs, int coeff_type,
                        int coeff_shift, int in_type, int fft_mode);
@@ -202,8 +207,8 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
  * K >= 1 and nspectra a multiple of K (else PPF_ERR_INVALID). K above 2^28,
  * or K*N above 2^24 on the two-pass path (whole groups of K spectra pass
  * through its workspace), is PPF_ERR_UNSUPPORTED. Alignment, overlap and
- * nspectra rules as ppf_execute. Plans in the matrix-core mode return
- * PPF_ERR_UNSUPPORTED.
+ * nspectra rules as ppf_execute. Plans in the matrix-core mode detect in
+ * the same epilogue, from their FP32-accumulated spectra.
  */
 int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K);
 

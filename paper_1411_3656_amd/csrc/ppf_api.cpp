@@ -178,6 +178,7 @@ struct ppf_plan_s {
     m.tw = d_tw;
     m.w256 = d_w256;
     m.d = 16 - T;
+    m.in_type = in_type == PPF_C16 ? 1 : 2;
     m.in_scale = std::ldexp(1.0f, -mfma_e1);
     m.out_scale = std::ldexp(1.0f, mfma_e1 - coeff_shift);
     return m;
@@ -308,6 +309,12 @@ int run_batch(ppf_plan_t p, hipStream_t stream, const void* x0, long long h0, co
 int run_power(ppf_plan_t p, hipStream_t stream, const void* in, float* pout, long long M, int K) {
   const ppf::PlanDev pd = p->dev();
   const size_t sb = (size_t)sample_bytes(p->in_type);
+  if (p->fft_mode == PPF_FFT_MFMA_F16) {
+    ppf::BatchArgs a{in, in, 0, nullptr, M};
+    hipError_t e = ppf::launch_mfma_power(p->mfma(), a, pout, K, stream);
+    if (e != hipSuccess) return fail_hip(e, "matrix-core power kernel launch");
+    return PPF_OK;
+  }
   if (p->path == PPF_PATH_FUSED) {
     ppf::BatchArgs a{in, in, 0, nullptr, M};
     hipError_t e = ppf::launch_fused_power(pd, a, pout, K, stream);
@@ -404,9 +411,9 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   }
   if (coeff_shift < 0 || coeff_shift > 30) { fail(PPF_ERR_INVALID, "coeff_shift=%d outside 0..30", coeff_shift); return nullptr; }
   if (fft_mode == PPF_FFT_MFMA_F16) {
-    if (!ppf::mfma_available(N, taps) || in_type != PPF_CI8 || coeff_type != PPF_R16) {
+    if (!ppf::mfma_available(N, taps) || (in_type != PPF_CI8 && in_type != PPF_C16) || coeff_type != PPF_R16) {
       fail(PPF_ERR_UNSUPPORTED,
-           "fft_mode=MFMA_F16 takes N=4096, taps <= 16, complex int8 input and FP16 coefficients "
+           "fft_mode=MFMA_F16 takes N=4096, taps <= 16, complex int8 or FP16 input and FP16 coefficients "
            "(got N=%d taps=%d in_type=%d coeff_type=%d)", N, taps, in_type, coeff_type);
       return nullptr;
     }
@@ -449,9 +456,10 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   if ((e = ppf::launch_twiddles(p->d_tw, N, nullptr)) != hipSuccess) goto hip_fail;
   if (fft_mode == PPF_FFT_MFMA_F16) {
     // FP16 coefficients in the kernel's lane order, and the sample scale:
-    // the largest FP16 stage input is at most 128 * 256 * S * 2^-e1 with
-    // S = max over channels of sum_t |h16[t][c]| (|x| <= 128 for int8 and
-    // two radix-16 stages of growth <= 16 each); e1 keeps it below 60000.
+    // the largest FP16 stage input is at most X * 256 * S * 2^-e1 with
+    // S = max over channels of sum_t |h16[t][c]|, X the largest input
+    // magnitude (128 for int8, 65504 for FP16: any finite FP16 input) and
+    // two radix-16 stages of growth <= 16 each; e1 keeps it below 60000.
     const uint16_t* h16 = (const uint16_t*)coeffs;
     std::vector<uint16_t> lane(ppf::mfma_coef_bytes() / 2);
     ppf::mfma_coef_layout(h16, taps, lane.data());
@@ -461,15 +469,19 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
       for (int t = 0; t < taps; ++t) sc += std::fabs((double)half_to_float(h16[(size_t)t * N + c]));
       smax = sc > smax ? sc : smax;
     }
-    // Bounds on e1: >= -8 keeps 128 * 2^-e1 in FP16 range, <= 24 keeps every
-    // int8 sample times 2^-e1 exact; the output scale 2^(e1-s) is folded into
-    // the FP16 stage-3 DFT matrix, exact for e1 - s in [-12, 15]. Among the
-    // admissible values the smallest (the most FP16 headroom used) is taken.
-    const int e1_range = smax > 0.0 ? (int)std::ceil(std::log2(128.0 * 256.0 * smax / 60000.0)) : -8;
+    // Bounds on e1: for int8, >= -8 keeps 128 * 2^-e1 in FP16 range and
+    // <= 24 keeps every sample times 2^-e1 exact (FP16 samples are not
+    // scaled themselves: the FIR's FP32 sums are); the output scale 2^(e1-s)
+    // is folded into the FP16 stage-3 DFT matrix, exact for e1 - s in
+    // [-12, 15]. Among the admissible values the smallest (the most FP16
+    // headroom used) is taken.
+    const double xmax = in_type == PPF_CI8 ? 128.0 : 65504.0;
+    const int e1_range = smax > 0.0 ? (int)std::ceil(std::log2(xmax * 256.0 * smax / 60000.0)) : -8;
     int e1 = e1_range;
     if (e1 < -8) e1 = -8;
     if (e1 < coeff_shift - 12) e1 = coeff_shift - 12;
-    const int e1_hi = coeff_shift + 15 < 24 ? coeff_shift + 15 : 24;
+    int e1_hi = coeff_shift + 15;
+    if (in_type == PPF_CI8 && e1_hi > 24) e1_hi = 24;
     if (e1 > e1_hi) {
       delete p;
       fail(PPF_ERR_UNSUPPORTED,
@@ -643,8 +655,6 @@ int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long lo
       return fail(PPF_ERR_UNSUPPORTED, "two-pass detection takes K*N <= 2^24 (K=%d, N=%d)", K, plan->N);
     if (nspectra < 0) return fail(PPF_ERR_INVALID, "nspectra=%lld is negative", nspectra);
     if (nspectra % K) return fail(PPF_ERR_INVALID, "nspectra=%lld is not a multiple of K=%d", nspectra, K);
-    if (plan->fft_mode == PPF_FFT_MFMA_F16)
-      return fail(PPF_ERR_UNSUPPORTED, "detection is not built for the matrix-core mode");
     if (nspectra == 0) { g_status = PPF_OK; return PPF_OK; }
     if (!in || !out_power) return fail(PPF_ERR_INVALID, "in or out_power is NULL");
     if (((uintptr_t)in & 15) || ((uintptr_t)out_power & 15))

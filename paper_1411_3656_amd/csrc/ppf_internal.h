@@ -101,13 +101,14 @@ hipError_t launch_fused_power(const PlanDev& pd, const BatchArgs& a, float* pout
 hipError_t launch_fft_power(const PlanDev& pd, const void* in, float* pout, long long M, int K, hipStream_t st);
 
 // Reduced-precision fused kernel with matrix-core DFT stages (N = 4096,
-// complex int8 input, FP16 coefficients).
+// complex int8 or FP16 input, FP16 coefficients).
 struct MfmaDev {
   const void* coef16;  // 16 tap slots x 4096 FP16 coefficients in lane order
   const void* tw;      // 4096 complex FP32 twiddles
   const void* w256;    // 256 complex FP16 values exp(-2 pi i k/256)
   int d;               // leading zero tap slots (16 - T)
-  float in_scale;      // 2^-e1 applied to the int8 samples (exact in FP16)
+  int in_type;         // 2 complex int8, 1 complex FP16
+  float in_scale;      // 2^-e1: on the int8 samples (exact in FP16), or on the FIR's FP32 sums
   float out_scale;     // 2^(e1 - coeff_shift), folded exactly into the FP16 stage-3 matrix
 };
 bool mfma_available(int N, int TP);
@@ -120,6 +121,8 @@ hipError_t launch_w256(void* table, hipStream_t st);
 hipError_t launch_design(int L, int N, int window, double beta, const double* user, double* v, float* h,
                          double* sum, hipStream_t st);
 hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st);
+// Detection with the matrix-core transform: |X|^2 summed over K spectra.
+hipError_t launch_mfma_power(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st);
 
 }  // namespace ppf
 

@@ -96,9 +96,11 @@ __device__ __forceinline__ uint32_t widen1(uint32_t raw, h2 sc, h2 bias) {
 }  // namespace
 
 struct MfmaParams {
-  const void* x0;            // complex int8, first segment (h0 blocks)
-  const void* x1;            // complex int8, second segment
+  const void* x0;            // complex int8 or FP16, first segment (h0 blocks)
+  const void* x1;            // second segment
   v2f* out;                  // complex FP32 spectra
+  float* pout;               // detection: |X|^2 summed over K spectra, (M / K) x N
+  int K;
   const uint4* coef;         // [16][4096] FP16 coefficients in lane order
   const v2f* tw;             // 4096 FP32 twiddles exp(-2 pi i k / 4096)
   const uint32_t* w256;      // 256 FP16 complex exp(-2 pi i k / 256), (re, im) packed
@@ -111,6 +113,12 @@ struct MfmaParams {
   float out_scale;           // 2^(e1 - s), exact on the FP16 stage-3 matrix
 };
 
+// Input types of the matrix-core kernel: complex int8 (2 bytes per sample,
+// scaled by 2^-e1 as it is widened, exactly) and complex FP16 (4 bytes, used
+// as stored; the FIR's FP32 sums are scaled by 2^-e1 instead, exactly).
+constexpr int kInI8 = 2;
+constexpr int kInF16 = 1;
+
 namespace {
 
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
@@ -119,8 +127,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return xcd * q + (xcd < rem ? xcd : rem) + k;
 }
 
-template <int PF, int AUX>
+template <int PF, int AUX, int IT, bool POW>
 struct MfmaEngine {
+  static constexpr int SB = IT == kInI8 ? 2 : 4;   // bytes per input sample
   static_assert(kTaps % PF == 0, "prefetch depth divides the ring");
   const MfmaParams& p;
   uint8_t* lds;
@@ -137,8 +146,8 @@ struct MfmaEngine {
   __device__ __forceinline__ MfmaEngine(const MfmaParams& p_, uint8_t* lds_) : p(p_), lds(lds_) {}
 
   __device__ __forceinline__ const uint8_t* block_ptr(int rb) const {
-    return rb < p.h0 ? (const uint8_t*)p.x0 + (size_t)rb * kN * 2
-                     : (const uint8_t*)p.x1 + (size_t)(rb - p.h0) * kN * 2;
+    return rb < p.h0 ? (const uint8_t*)p.x0 + (size_t)rb * kN * SB
+                     : (const uint8_t*)p.x1 + (size_t)(rb - p.h0) * kN * SB;
   }
 
   // raw int8 pairs of this lane's 4 channels of virtual block vb, one per
@@ -148,14 +157,20 @@ struct MfmaEngine {
   // its loads return zero without touching memory; no branch either.
   __device__ __forceinline__ void load(uint32_t (&dst)[4], int vb) const {
     const bool in = vb >= vb_lo && vb < vb_hi;
-    const __amdgpu_buffer_rsrc_t rs = rsrc(in ? block_ptr(vb - p.d) : p.x1, in ? kN * 2 : 0);
+    const __amdgpu_buffer_rsrc_t rs = rsrc(in ? block_ptr(vb - p.d) : p.x1, in ? kN * SB : 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dst[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, in_off, 512 * e, AUX);
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (IT == kInI8) dst[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, in_off, 256 * SB * e, AUX);
+      else dst[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, in_off, 256 * SB * e, AUX);
+    }
   }
 
   __device__ __forceinline__ void widen(const uint32_t (&raw)[4], uint32_t (&slot)[4]) const {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) slot[e] = widen1(raw[e], sc, bias);
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (IT == kInI8) slot[e] = widen1(raw[e], sc, bias);
+      else slot[e] = raw[e];   // packed FP16 (re, im) as stored
+    }
   }
 
   __device__ __forceinline__ void init(int lb) {
@@ -168,7 +183,7 @@ struct MfmaEngine {
     ng = rem < p.S ? rem : p.S;
     vb_lo = m0 > p.d ? m0 : p.d;
     vb_hi = m0 + ng + kTaps - 1;
-    in_off = (uint32_t)(16 * w + j + 1024 * h) * 2u;
+    in_off = (uint32_t)(16 * w + j + 1024 * h) * (uint32_t)SB;
     out_off = (uint32_t)(j + 16 * w + 1024 * h) * 8u;
     wr1 = kCoefBytes + swz(1024 * h + 16 * j + w) * 4;                 // in X
     wr2 = kCoefBytes + kXchgBytes + swz(1024 * h + 16 * w + j) * 4;    // in Y
@@ -247,6 +262,8 @@ struct MfmaEngine {
     return __builtin_bit_cast(h8, *(const uint4*)(lds + buf + rd));
   }
 
+  float pw[4] = {0.f, 0.f, 0.f, 0.f};   // detection sums
+
   __device__ __forceinline__ void run() {
     constexpr int X = kCoefBytes, Y = kCoefBytes + kXchgBytes;
 
@@ -308,6 +325,11 @@ struct MfmaEngine {
         h8 b;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
+          if constexpr (IT == kInF16) {
+            // FP16 samples enter unscaled: scale the FP32 sums (exact)
+            ar[e] *= p.in_scale;
+            ai[e] *= p.in_scale;
+          }
           b[2 * e] = (_Float16)ar[e];
           b[2 * e + 1] = (_Float16)ai[e];
         }
@@ -321,26 +343,45 @@ struct MfmaEngine {
         __syncthreads();
         dft16(a3, read_vec(Y), dre, dim);         // stage 3 over a, output scale folded in
 
-        const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * kN, it < ng ? kN * 8 : 0);
+        if constexpr (POW) {
+          // detection: this lane's four bins summed over K spectra (tiles
+          // start at multiples of K); steps past the tile add nothing
+          if (it < ng) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          v2f o;
-          o.x = dre[r];
-          o.y = dim[r];
-          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, o),
-                                                rs, out_off, (uint32_t)(2048 * r), kAuxNt);
+            for (int r = 0; r < 4; ++r) pw[r] += fmaf(dre[r], dre[r], dim[r] * dim[r]);
+            if ((m0 + it + 1) % p.K == 0) {
+              const long long q = (long long)(m0 + it) / p.K;
+              const __amdgpu_buffer_rsrc_t rs = rsrc(p.pout + q * kN, kN * 4);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw[r]), rs, out_off / 2,
+                                                      (uint32_t)(1024 * r), kAuxNt);
+                pw[r] = 0.f;
+              }
+            }
+          }
+        } else {
+          const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * kN, it < ng ? kN * 8 : 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            v2f o;
+            o.x = dre[r];
+            o.y = dim[r];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, o),
+                                                  rs, out_off, (uint32_t)(2048 * r), kAuxNt);
+          }
         }
       }
     }
   }
 };
 
-template <int PF, int AUX>
+template <int PF, int AUX, int IT, bool POW>
 __global__ void __launch_bounds__(kThreads) ppf_mfma_kernel(MfmaParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds_mfma[];
   const int lb = xcd_tile(blockIdx.x, p.nblocks);
   if (lb * p.S >= p.M) return;    // whole block idle
-  MfmaEngine<PF, AUX> eng(p, lds_mfma);
+  MfmaEngine<PF, AUX, IT, POW> eng(p, lds_mfma);
   eng.init(lb);
   eng.run();
 }
@@ -364,7 +405,8 @@ __global__ void ppf_w256_kernel(uint32_t* t) {
 #define PPF_MFMA_NT 0
 #endif
 using MfmaKernel = void (*)(MfmaParams);
-constexpr MfmaKernel kMfmaKernel = ppf_mfma_kernel<PPF_MFMA_PF, PPF_MFMA_NT ? kAuxNt : 0>;
+template <int IT, bool POW>
+constexpr MfmaKernel mfma_kernel() { return ppf_mfma_kernel<PPF_MFMA_PF, PPF_MFMA_NT ? kAuxNt : 0, IT, POW>; }
 
 int cu_count() {
   static int n = 0;
@@ -400,49 +442,74 @@ hipError_t launch_w256(void* table, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st) {
+namespace {
+
+template <int IT, bool POW>
+hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st) {
   if (a.M <= 0) return hipSuccess;
+  constexpr MfmaKernel kern = mfma_kernel<IT, POW>();
+  constexpr int SB = IT == kInI8 ? 2 : 4;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)kMfmaKernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
   // one workgroup per CU (the LDS holds a single one); split larger
-  // batches into launches whose spectrum indices fit in 32 bits
-  const long long kMaxLaunch = 1ll << 28;
+  // batches into launches whose spectrum indices fit in 32 bits (whole
+  // groups of K spectra when detecting)
+  const long long kMaxLaunch = POW ? (1ll << 28) / K * K : (1ll << 28);
   for (long long s0 = 0; s0 < a.M; s0 += kMaxLaunch) {
     const long long k = a.M - s0 < kMaxLaunch ? a.M - s0 : kMaxLaunch;
     MfmaParams p;
     if (s0 < a.h0) {
-      p.x0 = (const uint8_t*)a.x0 + (size_t)s0 * kN * 2;
+      p.x0 = (const uint8_t*)a.x0 + (size_t)s0 * kN * SB;
       p.h0 = (int)(a.h0 - s0);
       p.x1 = a.x1;
     } else {
       p.x0 = a.x1;
       p.h0 = 0;
-      p.x1 = (const uint8_t*)a.x1 + (size_t)(s0 - a.h0) * kN * 2;
+      p.x1 = (const uint8_t*)a.x1 + (size_t)(s0 - a.h0) * kN * SB;
     }
-    p.out = (v2f*)a.out + (size_t)s0 * kN;
+    p.out = POW ? nullptr : (v2f*)a.out + (size_t)s0 * kN;
+    p.pout = POW ? pout + (size_t)(s0 / K) * kN : nullptr;
+    p.K = K;
     p.coef = (const uint4*)md.coef16;
     p.tw = (const v2f*)md.tw;
     p.w256 = (const uint32_t*)md.w256;
     p.M = (int)k;
-    // tiles of a multiple of 16 spectra (the unrolled step count), about
-    // one per CU
+    // tiles of a multiple of 16 spectra (the unrolled step count), and of K
+    // when detecting, about one per CU
     const int cus = cu_count();
     long long S = (k + cus - 1) / cus;
     S = (S + 15) / 16 * 16;
+    if (POW) {
+      long long unit = 16;
+      while (unit % K) unit += 16;   // lcm(16, K)
+      S = (S + unit - 1) / unit * unit;
+    }
     p.S = (int)S;
     p.nblocks = (int)((k + S - 1) / S);
     p.d = md.d;
     p.in_scale = md.in_scale;
     p.out_scale = md.out_scale;
-    hipLaunchKernelGGL(kMfmaKernel, dim3(p.nblocks), dim3(kThreads), kLdsBytes, st, p);
+    hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kThreads), kLdsBytes, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st) {
+  return md.in_type == kInF16 ? mfma_launch<kInF16, false>(md, a, nullptr, 1, st)
+                              : mfma_launch<kInI8, false>(md, a, nullptr, 1, st);
+}
+
+hipError_t launch_mfma_power(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st) {
+  return md.in_type == kInF16 ? mfma_launch<kInF16, true>(md, a, pout, K, st)
+                              : mfma_launch<kInI8, true>(md, a, pout, K, st);
 }
 
 }  // namespace ppf

@@ -23,8 +23,11 @@ and values are rounded where the kernel rounds them:
     twiddle multiply with exp(-2 pi i k/4096) rounded to FP32, are rounded
     to FP32.
 The sample scale e1 follows the plan's rule: the smallest power that keeps
-every FP16 stage input below 60000 for any int8 input (|x| <= 128, growth
-<= 16 per stage), at least -8, at least s - 12, and at most min(24, s + 15).
+every FP16 stage input below 60000 for any input (|x| <= 128 for int8,
+65504 for FP16; growth <= 16 per stage), at least -8, at least s - 12, and
+at most s + 15 (and 24 for int8). int8 samples are scaled as they are
+widened, FP16 samples enter as stored and the FP32 sums are scaled; both
+scalings are exact powers of two, so the model scales the samples.
 """
 
 from __future__ import annotations
@@ -36,12 +39,13 @@ import numpy as np
 N = 4096
 
 
-def sample_exponent(h16: np.ndarray, shift: int, taps: int) -> int:
+def sample_exponent(h16: np.ndarray, shift: int, taps: int, fp16_input: bool = False) -> int:
     h = np.abs(h16.astype(np.float64)).reshape(taps, N)
     smax = float(h.sum(axis=0).max())
-    e1 = math.ceil(math.log2(128.0 * 256.0 * smax / 60000.0)) if smax > 0 else -8
+    xmax = 65504.0 if fp16_input else 128.0
+    e1 = math.ceil(math.log2(xmax * 256.0 * smax / 60000.0)) if smax > 0 else -8
     e1 = max(e1, -8, shift - 12)
-    if e1 > min(shift + 15, 24):
+    if e1 > (shift + 15 if fp16_input else min(shift + 15, 24)):
         raise ValueError("coefficients outside the matrix-core scaling window")
     return e1
 
@@ -70,8 +74,8 @@ def w256_fp16() -> np.ndarray:
 def model(x_int8: np.ndarray, h16: np.ndarray, shift: int, taps: int, spectra, exact: bool = False) -> np.ndarray:
     """The modelled matrix-core output for the listed spectra (complex128).
 
-    x_int8: (L, 2) int8 (re, im) pairs; h16: FP16 coefficients h[t*N + c]
-    scaled by 2^shift. exact=True drops every rounding (the factorisation
+    x_int8: (L, 2) int8 or float16 (re, im) pairs; h16: FP16 coefficients
+    h[t*N + c] scaled by 2^shift. exact=True drops every rounding (the factorisation
     alone, which must reproduce the plain DFT).
     """
     global _EXACT
@@ -83,7 +87,7 @@ def model(x_int8: np.ndarray, h16: np.ndarray, shift: int, taps: int, spectra, e
 
 
 def _model(x_int8, h16, shift, taps, spectra):
-    e1 = sample_exponent(h16, shift, taps)
+    e1 = sample_exponent(h16, shift, taps, fp16_input=x_int8.dtype == np.float16)
     m_idx = np.asarray(list(spectra), dtype=np.int64)
     xs = (x_int8[:, 0].astype(np.float64) + 1j * x_int8[:, 1].astype(np.float64)) * 2.0 ** -e1
     blocks = xs.reshape(-1, N)

@@ -164,3 +164,90 @@ def test_matches_the_rounding_model():
     print(f"  GPU {s_gpu:.2f} dB, model {s_mod:.2f} dB, GPU vs model {s_gap:.2f} dB", flush=True)
     assert abs(s_gpu - s_mod) <= 0.5
     assert s_gap >= s_mod + 6.0
+
+
+def _fp16_input(n_samples, seed):
+    return signals.to_complex_fp16(signals.complex_gaussian(n_samples, 1.0, seed))
+
+
+def mfma_plan_in(h16, taps, shift, in_type):
+    return ppf.Plan(N, taps, h16, in_type=in_type, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+
+
+@pytest.mark.parametrize("taps,m_total", [(16, 37), (16, 300), (8, 41)])
+def test_fp16_input(taps, m_total):
+    """Complex FP16 input on the matrix-core stages: any finite FP16 sample
+    is admitted (the scale is set for |x| <= 65504, so no stage input can
+    overflow); at sigma 1 the same bars hold, and the FP32 path on the same
+    FP16 values is reported beside it."""
+    torch = _torch()
+    from tests import mfma_model
+    print(f"case mfma fp16 input T={taps} M={m_total}", flush=True)
+    h16, shift, h_exact = fp16_coeffs(taps)
+    x = _fp16_input((m_total + taps - 1) * N, seed=800 + taps + m_total)
+    xd = torch.from_numpy(x).cuda()
+    plan = mfma_plan_in(h16, taps, shift, ppf.PPF_C16)
+    got = plan.execute(xd)
+    plan32 = ppf.Plan(N, taps, h16, in_type=ppf.PPF_C16, coeff_shift=shift)     # FP32 DFT stages
+    got32 = plan32.execute(xd)
+    torch.cuda.synchronize()
+    plan.close()
+    plan32.close()
+    pick = list(range(m_total)) if m_total <= 41 else sorted(set(range(0, m_total, 7)) | {1, m_total - 1})
+    ref = oracle.ppf(x, h_exact, N, taps, spectra=pick)
+    g = got.cpu().numpy()[pick]
+    check(g, ref, f"fp16 input T={taps}")
+    mod = mfma_model.model(x, h16, shift, taps, pick)
+    print(f"  model {snr_db(mod, ref):.2f} dB; FP32 DFT path on the same input: "
+          f"SNR {snr_db(got32.cpu().numpy()[pick], ref):.1f} dB, max err/rms {rel_err(got32.cpu().numpy()[pick], ref):.2e}",
+          flush=True)
+    assert abs(snr_db(g, ref) - snr_db(mod, ref)) <= 0.5
+    assert rel_err(got32.cpu().numpy()[pick], ref) <= 1e-5
+
+
+def test_fp16_input_extremes_do_not_overflow():
+    """FP16 samples at the format's largest magnitude give finite spectra
+    (the scale bounds every stage input below the FP16 range)."""
+    torch = _torch()
+    taps, m_total = 16, 20
+    h16, shift, h_exact = fp16_coeffs(taps)
+    rng = np.random.default_rng(3)
+    x = np.empty(((m_total + taps - 1) * N, 2), np.float16)
+    x[:] = rng.choice(np.array([65504.0, -65504.0], np.float16), size=x.shape)
+    plan = mfma_plan_in(h16, taps, shift, ppf.PPF_C16)
+    got = plan.execute(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    plan.close()
+    got = got.cpu().numpy()
+    assert np.isfinite(got).all()
+    ref = oracle.ppf(x, h_exact, N, taps)
+    s = snr_db(got, ref)
+    print(f"  full-scale FP16 input: SNR {s:.1f} dB", flush=True)
+    assert s >= MIN_SNR_DB
+
+
+@pytest.mark.parametrize("in_type,k_int,m_total", [(ppf.PPF_CI8, 16, 320), (ppf.PPF_C16, 4, 100), (ppf.PPF_CI8, 3, 60)])
+def test_detection_in_matrix_core_mode(in_type, k_int, m_total):
+    """|X|^2 summed over K spectra in the matrix-core kernel's epilogue,
+    against the oracle's detected power on the same input; its error is that
+    of the modelled matrix-core spectra, detected the same way."""
+    torch = _torch()
+    from tests import mfma_model
+    taps = 16
+    print(f"case mfma detection in={in_type} K={k_int} M={m_total}", flush=True)
+    h16, shift, h_exact = fp16_coeffs(taps)
+    n_samples = (m_total + taps - 1) * N
+    x = signals.int8_input(n_samples, seed=900 + k_int, sigma=16.0) if in_type == ppf.PPF_CI8 \
+        else _fp16_input(n_samples, seed=900 + k_int)
+    plan = mfma_plan_in(h16, taps, shift, in_type)
+    got = plan.execute_power(torch.from_numpy(x).cuda(), k_int)
+    torch.cuda.synchronize()
+    plan.close()
+    got = got.cpu().numpy().astype(np.float64)
+    ref = oracle.ppf_power(x, h_exact, N, taps, k_int)
+    mod_x = mfma_model.model(x, h16, shift, taps, range(m_total))
+    mod = (np.abs(mod_x) ** 2).reshape(m_total // k_int, k_int, N).sum(axis=1)
+    rel = lambda p: float(np.sqrt(np.mean((p - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    print(f"  detected power: rms rel error GPU {rel(got):.2e}, model {rel(mod):.2e}", flush=True)
+    assert got.shape == ref.shape
+    assert rel(got) <= 1.5 * rel(mod) + 1e-6

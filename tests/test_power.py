@@ -85,9 +85,14 @@ def test_power_argument_errors():
     mplan = ppf.Plan(4096, 16, h16, in_type=ppf.PPF_CI8, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
     xi = torch.zeros((31 * 4096, 2), dtype=torch.int8, device="cuda")
     po = torch.zeros((16, 4096), dtype=torch.float32, device="cuda")
+    # the matrix-core mode detects in its own epilogue, with the same rules
     with pytest.raises(ppf.PPFError) as ei:
-        ppf.ppf_execute_power(mplan.handle, xi, po, 16, 1)
-    assert ei.value.status == ppf.PPF_ERR_UNSUPPORTED
+        ppf.ppf_execute_power(mplan.handle, xi, po, 16, 3)
+    assert ei.value.status == ppf.PPF_ERR_INVALID
+    po.fill_(float("nan"))
+    assert ppf.ppf_execute_power(mplan.handle, xi, po, 16, 1) == ppf.PPF_OK
+    torch.cuda.synchronize()
+    assert bool((po == 0).all())                                   # zero input, zero power
     mplan.close()
 
 
