@@ -8,7 +8,9 @@
 // spectra. Payloads are complex Gaussian (sigma 1) staged in device memory
 // beforehand, so the measurement excludes host transfers. The producer
 // submits each chunk at its scheduled arrival time and latency is measured
-// from that time, so a late producer counts against the server. Prints one
+// from that time, so a late producer counts against the server. Several
+// producer threads (--producers, default 4) share the streams, so that the
+// offered rate is not capped by one thread's submission rate. Prints one
 // JSON line of throughput and latency.
 //
 // Checked mode (--check-dir D): the coefficients of every plan come from
@@ -23,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -152,6 +155,8 @@ int main(int argc, char** argv) {
   // restrict the (N, T) mix: --only-n 1024 --only-t 8 (diagnostics)
   const int only_n = (int)arg_d(argc, argv, "--only-n", 0);
   const int only_t = (int)arg_d(argc, argv, "--only-t", 0);
+  // submitting threads (one thread tops out near 2M submissions per second)
+  const int producers = std::max(1, std::min(16, (int)arg_d(argc, argv, "--producers", 4)));
   const std::string check_dir = arg_s(argc, argv, "--check-dir");
   // checked streams: index -> (N, T, samples)
   std::map<int, std::vector<long long>> checked;
@@ -247,46 +252,62 @@ int main(int argc, char** argv) {
     }
   });
 
-  Rng arr(seed ^ 0xA5A5A5A5ull);
-  long long submitted = 0, late = 0;
+  // P producer threads, producer q owning the streams i with i % P == q
+  // and offering 1/P of the load as its own Poisson process (together one
+  // Poisson process of rate lambda over uniformly chosen streams); each
+  // stream's chunks therefore come from one thread, in order.
+  std::atomic<long long> submitted{0}, late{0};
   const long long t0 = ppf_clock_ns() + 1000000;        // start 1 ms from now
   const long long t_meas = t0 + (long long)(warmup * 1e9);
   const long long t_end = t_meas + (long long)(seconds * 1e9);
-  bool reset_done = false;
-  double t_next = (double)t0;
-  while (true) {
-    t_next += -log(1.0 - arr.uniform()) / lambda * 1e9;
-    const long long ta = (long long)t_next;
-    if (ta >= t_end) break;
-    if (!reset_done && ta >= t_meas) {
-      PK(ppf_server_reset_stats(srv));
-      reset_done = true;
+  auto produce = [&](int q) {
+    Rng arr(seed ^ 0xA5A5A5A5ull ^ (0x9E3779B97F4A7C15ull * (uint64_t)q));
+    std::vector<int> mine;
+    for (int i = q; i < nstreams; i += producers) mine.push_back(i);
+    if (mine.empty()) return;
+    const double lam = lambda * (double)mine.size() / nstreams;
+    bool reset_done = q != 0;
+    double t_next = (double)t0;
+    long long count = 0, nlate = 0;
+    while (true) {
+      t_next += -log(1.0 - arr.uniform()) / lam * 1e9;
+      const long long ta = (long long)t_next;
+      if (ta >= t_end) break;
+      if (!reset_done && ta >= t_meas) {
+        PK(ppf_server_reset_stats(srv));
+        reset_done = true;
+      }
+      Stream& st = streams[mine[arr.range(0, (int)mine.size() - 1)]];
+      const int S = arr.range(1, max_s);
+      ppf_chunk c;
+      c.nspectra = S;
+      c.tag = ((unsigned long long)q << 48) | (unsigned long long)count;
+      if (st.chk_in && !st.chk_done && st.chk_pos + S <= st.chk_spectra) {
+        c.in = st.chk_in + st.chk_pos * st.N;
+        c.out = st.chk_out + st.chk_pos * st.N;
+        st.chk_pos += S;
+      } else {
+        // a checked stream whose input is used up stays on the ring from here
+        st.chk_done = true;
+        if (st.in_pos + S > st.ring_spectra) st.in_pos = 0;
+        if (st.out_pos + S > st.ring_spectra) st.out_pos = 0;
+        c.in = st.in + st.in_pos * st.N;
+        c.out = st.out + st.out_pos * st.N;
+        st.in_pos += S;
+        st.out_pos += S;
+      }
+      long long now = ppf_clock_ns();
+      while (now < ta) now = ppf_clock_ns();
+      if (now - ta > 20000) nlate++;
+      PK(ppf_server_submit(st.h, &c, ta));
+      count++;
     }
-    Stream& st = streams[arr.range(0, nstreams - 1)];
-    const int S = arr.range(1, max_s);
-    ppf_chunk c;
-    c.nspectra = S;
-    c.tag = (unsigned long long)submitted;
-    if (st.chk_in && !st.chk_done && st.chk_pos + S <= st.chk_spectra) {
-      c.in = st.chk_in + st.chk_pos * st.N;
-      c.out = st.chk_out + st.chk_pos * st.N;
-      st.chk_pos += S;
-    } else {
-      // a checked stream whose input is used up stays on the ring from here
-      st.chk_done = true;
-      if (st.in_pos + S > st.ring_spectra) st.in_pos = 0;
-      if (st.out_pos + S > st.ring_spectra) st.out_pos = 0;
-      c.in = st.in + st.in_pos * st.N;
-      c.out = st.out + st.out_pos * st.N;
-      st.in_pos += S;
-      st.out_pos += S;
-    }
-    long long now = ppf_clock_ns();
-    while (now < ta) now = ppf_clock_ns();
-    if (now - ta > 20000) late++;
-    PK(ppf_server_submit(st.h, &c, ta));
-    submitted++;
-  }
+    submitted += count;
+    late += nlate;
+  };
+  std::vector<std::thread> prod;
+  for (int q = 0; q < producers; ++q) prod.emplace_back(produce, q);
+  for (auto& t : prod) t.join();
   const int drain_status = ppf_server_drain(srv, 60.0);
   stop_poll = true;
   poller.join();
@@ -313,11 +334,11 @@ int main(int argc, char** argv) {
          "\"sustained_gbps\": %.2f, \"realtime_multiple\": %.2f, \"p50_us\": %.1f, \"p99_us\": %.1f, "
          "\"max_us\": %.1f, \"mean_us\": %.1f, \"chunks\": %lld, \"batches\": %lld, \"mean_batch_chunks\": %.1f, "
          "\"chunk_rate_per_s\": %.0f, \"streams\": %d, \"mean_n\": %.1f, \"seconds\": %g, \"late_submits\": %lld, "
-         "\"drain_status\": %d, \"state_bytes_used\": %lld, \"mean_batch_gpu_us\": %.1f, \"mean_form_us\": %.1f, "
+         "\"drain_status\": %d, \"producers\": %d, \"state_bytes_used\": %lld, \"mean_batch_gpu_us\": %.1f, \"mean_form_us\": %.1f, "
          "\"mean_launch_us\": %.1f, \"checked_spectra\": %lld, \"tags_dropped\": %lld}\n",
          nstreams, load, load, offered, s.input_gbps, s.input_gbps / 6.5, s.p50_us, s.p99_us, s.max_us,
          s.mean_us, s.chunks_done, s.batches, s.mean_batch_chunks, s.elapsed_s > 0 ? s.chunks_done / s.elapsed_s : 0.0,
-         nstreams, mean_n, seconds, late, drain_status, s.state_bytes_used, s.mean_batch_gpu_us, s.mean_form_us,
+         nstreams, mean_n, seconds, late.load(), drain_status, producers, s.state_bytes_used, s.mean_batch_gpu_us, s.mean_form_us,
          s.mean_launch_us, checked_chunks_spectra, s.tags_dropped);
   fflush(stdout);
   for (auto& st : streams) PK(ppf_stream_destroy(st.h));
