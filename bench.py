@@ -211,7 +211,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c4", "sweep", "copy", "serve", "serve_sweep", "mb", "detect"])
+                    choices=["c1", "c2", "c2_reduced", "c4", "sweep", "copy", "serve", "serve_sweep", "mb", "detect"])
     ap.add_argument("--k-int", type=int, default=16, help="detect: spectra integrated per power spectrum")
     ap.add_argument("--load", type=float, default=50.0, help="serving: offered load in multiples of 6.5 GB/s")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
@@ -285,6 +285,37 @@ def main() -> int:
                                         "samples_per_s": round(n * m_total / (ms32 * 1e-3), 1),
                                         "path": {1: "fused", 2: "two_pass"}.get(used32)}
         print(json.dumps(rec), flush=True)
+        return 0
+
+    if args.workload == "c2_reduced":
+        # C2's shape (N=1024, T=8, 2^27 samples) with complex int8 and complex
+        # FP16 input and FP16 coefficients, widened to FP32 in the fused
+        # kernel's loads: input bytes 2 or 4 per sample instead of 8.
+        n, taps, n_samples = 1024, 8, 1 << 27
+        m_total = n_samples // n - taps + 1
+        h64 = signals.design_coeffs(n, taps, "hamming")
+        h16, shift = signals.coeffs_fp16(h64)
+        for kind, name, sb, seed in ((ppf.PPF_CI8, "int8", 2, 5), (ppf.PPF_C16, "fp16", 4, 6)):
+            if kind == ppf.PPF_CI8:
+                x = signals.int8_input(n_samples, seed=signals.SEED_BASE + seed, sigma=16.0)
+            else:
+                x = signals.to_complex_fp16(signals.complex_gaussian(n_samples, 1.0, seed=signals.SEED_BASE + seed))
+            x_dev = torch.from_numpy(x).cuda()
+            del x
+            ms, used = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup, path,
+                                 in_type=kind, coeff_shift=shift)
+            rec = line(f"ska_lfaa_n1024_t8_2p27_{name}_in", n, taps, m_total, ms, used, args.steps, args.warmup)
+            in_b = metrics.input_bytes(n, m_total, sb)
+            rec["value"] = round(in_b / (ms * 1e-3) / 1e9, 3)
+            rec["realtime_multiple"] = round(metrics.realtime_multiple(rec["value"] * 1e9), 2)
+            rec["dtype"] = f"{'ci8' if sb == 2 else 'c16'}_in/f16_coef/f32"
+            alg = metrics.algorithmic_bytes(n, taps, m_total, in_bytes=sb, out_bytes=8, coeff_bytes=2)
+            rec["roofline"].update({"achieved": round(alg / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": alg})
+            rec["roofline"]["frac"] = round(rec["roofline"]["achieved"] / rec["roofline"]["peak"], 4)
+            rec["samples_per_s"] = round(n * m_total / (ms * 1e-3), 1)
+            print(json.dumps(rec), flush=True)
+            del x_dev
+            torch.cuda.empty_cache()
         return 0
 
     if args.workload == "detect":

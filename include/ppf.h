@@ -122,8 +122,10 @@ ppf_plan_t ppf_plan(int n_channels, int taps, const float* coeffs);
  * coeff_shift: the stored coefficients are h * 2^coeff_shift; the FP32
  *         accumulation is scaled by 2^-coeff_shift. Must be 0 for PPF_R32;
  *         0..30 for PPF_R16.
- * in_type: PPF_C32, PPF_C16 or PPF_CI8. Inputs are converted to FP32 in
- *         registers; the FIR accumulates in FP32. Output is always C32.
+ * in_type: PPF_C32, PPF_C16 or PPF_CI8. Inputs are converted exactly to
+ *         FP32 in registers as they are loaded (by the fused kernel where
+ *         the shape has one, else by the FIR pass of the two-pass form);
+ *         the FIR accumulates in FP32. Output is always C32.
  * fft_mode: PPF_FFT_F32 or PPF_FFT_MFMA_F16 (PPF_ERR_UNSUPPORTED where the
  *         MFMA stages are not built for N). The matrix-core mode is built
  *         for N = 4096 = 16^3, T <= 16, PPF_R16 coefficients and PPF_CI8 or
@@ -208,7 +210,8 @@ int ppf_execute_host(ppf_plan_t plan, const void* host_in, void* host_out, long 
  * or K*N above 2^24 on the two-pass path (whole groups of K spectra pass
  * through its workspace), is PPF_ERR_UNSUPPORTED. Alignment, overlap and
  * nspectra rules as ppf_execute. Plans in the matrix-core mode detect in
- * the same epilogue, from their FP32-accumulated spectra.
+ * the same epilogue, from their FP32-accumulated spectra; FP32-DFT plans
+ * with FP16 or int8 input detect in the two-pass form.
  */
 int ppf_execute_power(ppf_plan_t plan, const void* in, float* out_power, long long nspectra, int K);
 

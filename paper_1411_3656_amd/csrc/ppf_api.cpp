@@ -78,7 +78,8 @@ float half_to_float(uint16_t h) {
 // The fused kernels read complex FP32 input; other input types take the
 // two-pass path, whose FIR pass widens them as it loads.
 bool fused_ok_for(int N, int TP, int in_type) {
-  return in_type == PPF_C32 && (ppf::fused_available(N, TP) || TP == 1);
+  (void)in_type;   // FP16 and int8 input are widened in the fused kernels' loads
+  return ppf::fused_available(N, TP) || TP == 1;
 }
 
 // Largest FIR workspace of the two-pass path, in bytes (stays inside the
@@ -315,7 +316,7 @@ int run_power(ppf_plan_t p, hipStream_t stream, const void* in, float* pout, lon
     if (e != hipSuccess) return fail_hip(e, "matrix-core power kernel launch");
     return PPF_OK;
   }
-  if (p->path == PPF_PATH_FUSED) {
+  if (p->path == PPF_PATH_FUSED && p->in_type == PPF_C32) {
     ppf::BatchArgs a{in, in, 0, nullptr, M};
     hipError_t e = ppf::launch_fused_power(pd, a, pout, K, stream);
     if (e != hipSuccess) return fail_hip(e, "fused power kernel launch");

@@ -238,21 +238,28 @@ struct GroupFft {
   static constexpr int tw_off(int S) { return TWG ? tw_offset_twg(N, R, RX, S) : tw_offset(N, R, RX, S); }
   // stage S reads its twiddles from the table when it starts
   static constexpr bool tw_fetched(int S) { return TWG && S > 0 && (!TWR || ns_at(N, RX, S) > W); }
-  static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
+  // TWL: the table-twiddle mode reads a copy of the table in LDS (after
+  // the exchange planes) where it fits, at LDS rather than memory latency
+  static constexpr bool TWL = TWG && N <= 4096;
+  static constexpr size_t planes_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
+  static constexpr size_t lds_bytes() { return planes_bytes() + (TWL ? size_t(N) * sizeof(v2f) : 0); }
   static constexpr bool IL = lds_b64(N);             // interleaved (re, im) elements
-  // XL (large N, 16 or 32 elements per thread): swz64 is linear, changes
+  // XL (N >= 4096 with a multiple of 512 threads per group: 16 or 32
+  // elements per thread at N >= 8192, 4 over 1024 threads in the fused
+  // N = 4096 kernel, where every e*W is a multiple of 512): swz64 is linear, changes
   // only bits 0-4 and depends only on bits 5-8, and a Stockham stage's
   // element index is the thread's base with the q digit (and the
   // butterfly's offset) in bits of their own; so an element's address is
   // one base per stage XORed with swz64 of its offset, which is a plain
   // add for offsets that are multiples of 512. One base register per stage
   // instead of one per element keeps the register file for the elements.
-  static constexpr bool XL = IL && N >= 8192 && W == 512;
+  static constexpr bool XL = IL && N >= 4096 && W % 512 == 0;
 
   float* lds;      // shared memory base of the block
   int grp, j;
   int par;         // buffer of the next exchange (double-buffered mode)
   const v2f* tw;   // twiddle table (global)
+  uint32_t twl;    // TWL: LDS byte address of the table's copy
   v2f twr[NTW];
   int rb;          // XL: swizzled element j (the reads of every stage add e*W)
   int wb[L];       // XL: swizzled first write element of each stage
@@ -286,6 +293,12 @@ struct GroupFft {
 
   __device__ __forceinline__ void init(float* smem, int grp_, int j_, const v2f* tw_) {
     lds = smem; grp = grp_; j = j_; par = 0; tw = tw_;
+    if constexpr (TWL) {
+      v2f* t = (v2f*)((char*)smem + planes_bytes());
+      for (int i = threadIdx.x; i < N; i += blockDim.x) t[i] = tw_[i];
+      __syncthreads();
+      twl = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) v2f*)t;
+    }
     if constexpr (XL) {
       rb = swz64(j);
 #pragma unroll
@@ -313,11 +326,22 @@ struct GroupFft {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     int z;
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    // TWL: the LDS addresses are formed here from an opaque copy of j, so
+    // no per-stage address stays live across the spectrum loop
+    int jj = j;
+    if constexpr (TWL) asm volatile("" : "+v"(jj));
 #pragma unroll
     for (int ib = 0; ib < stage_sets<S>(); ++ib) {
-      const int k = (j + ib * W) % Ns;
+      const int k = (jj + ib * W) % Ns;
 #pragma unroll
-      for (int q = 1; q < r; ++q) tl[ib * (r - 1) + q - 1] = tw[k * q * (N / (Ns * r)) + z];
+      for (int q = 1; q < r; ++q) {
+        if constexpr (TWL) {
+          tl[ib * (r - 1) + q - 1] = *(const __attribute__((address_space(3))) v2f*)(uintptr_t)(
+              twl + (uint32_t)((k * q * (N / (Ns * r)) + z) * (int)sizeof(v2f)));
+        } else {
+          tl[ib * (r - 1) + q - 1] = tw[k * q * (N / (Ns * r)) + z];
+        }
+      }
     }
   }
 
@@ -525,6 +549,76 @@ __device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
                    : (rb < a.h01 ? a.x1 + (long long)(rb - a.h0) * N : a.x2 + (long long)(rb - a.h01) * N);
 }
 
+// Stored complex input types, widened to FP32 as they are loaded:
+// 0 = complex FP32, 1 = complex FP16, 2 = complex int8 (exact conversions).
+constexpr int in_bytes(int IT) { return IT == 0 ? 8 : (IT == 1 ? 4 : 2); }
+
+// block rb of the tile's input, for samples of SB bytes
+template <int N, int SB>
+__device__ __forceinline__ const char* block_addr(const TileArgs& a, int rb) {
+  const char* x0 = (const char*)a.x0;
+  const char* x1 = (const char*)a.x1;
+  const char* x2 = (const char*)a.x2;
+  return rb < a.h0 ? x0 + (long long)rb * N * SB
+                   : (rb < a.h01 ? x1 + (long long)(rb - a.h0) * N * SB : x2 + (long long)(rb - a.h01) * N * SB);
+}
+
+__device__ __forceinline__ v2f widen_c16(uint32_t w) {
+  _Float16 re, im;
+  const uint16_t lo = (uint16_t)(w & 0xFFFFu), hi = (uint16_t)(w >> 16);
+  __builtin_memcpy(&re, &lo, 2);
+  __builtin_memcpy(&im, &hi, 2);
+  v2f r;
+  r.x = (float)re;
+  r.y = (float)im;
+  return r;
+}
+__device__ __forceinline__ v2f widen_ci8(uint32_t w) {
+  v2f r;
+  r.x = (float)(int)(int8_t)(w & 0xFFu);
+  r.y = (float)(int)(int8_t)((w >> 8) & 0xFFu);
+  return r;
+}
+
+template <int IT>
+__device__ __forceinline__ v2f load_sample(const void* base, long long i) {
+  if constexpr (IT == 0) {
+    return ((const v2f*)base)[i];
+  } else if constexpr (IT == 1) {
+    return widen_c16(((const uint32_t*)base)[i]);
+  } else {
+    return widen_ci8(((const uint16_t*)base)[i]);
+  }
+}
+
+// Fused FIR + FFT at N = 4096 with up to 8 taps: four channels per lane
+// over a 1024-thread block, so that a lane's tap window (8 taps x 4
+// channels) is the same size as at N = 1024. Build-time switch (tuning).
+#ifndef PPF_FUSED_4096
+#define PPF_FUSED_4096 1
+#endif
+constexpr bool fused4096(int N, int TP) { return PPF_FUSED_4096 && N == 4096 && TP > 1 && TP <= 8; }
+// With 5..8 taps a ring of TP + 2 blocks, the coefficients (8 x 4 per
+// lane) and the twiddles exceed the 128 registers of a lane at 4 waves per
+// SIMD: the ring holds exactly the tap window, the block the next step
+// needs is loaded into the slot the FIR has just consumed (so the load runs
+// during the FFT), and the twiddles are read per stage from a copy of the
+// table in LDS. (Coefficients in LDS instead measured 26% of HBM peak at
+// T = 8 against 39% for this.)
+#ifndef PPF_LATE_MIN_TP
+#define PPF_LATE_MIN_TP 8
+#endif
+#ifndef PPF_F4096_T8
+#define PPF_F4096_T8 0
+#endif
+#ifndef PPF_F4096_PF
+#define PPF_F4096_PF 1
+#endif
+constexpr bool fused4096_late(int N, int TP) {
+  return PPF_F4096_T8 == 0 && fused4096(N, TP) && TP >= PPF_LATE_MIN_TP;
+}
+constexpr bool fused4096_cl(int N, int TP) { return PPF_F4096_T8 == 1 && fused4096(N, TP) && TP == 8; }
+
 // Per-block engine of the fused kernel: coefficients, twiddles and lane
 // offsets are loaded once and reused by every tile the block processes.
 //
@@ -535,18 +629,25 @@ __device__ __forceinline__ const v2f* block_ptr(const TileArgs& a, int rb) {
 // blocks of each step are loads running ahead.
 // UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
 // presum is the loaded block itself and no coefficients are held.
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false>
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false,
+          int IT = 0>
 struct FusedEngine {
   static constexpr int W = N / R;
+  static constexpr int SB = in_bytes(IT);   // bytes per stored input sample
+  static_assert(!UNIT || IT == 0, "the FFT pass reads FP32 presums");
   static constexpr int Q = TP + PF;
   static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
+  // LATE: the ring is the tap window alone (no prefetch slots); each step
+  // loads the block the next step needs into the slot its FIR has just
+  // read, after the FIR and before the FFT, which covers the load.
+  static constexpr bool LATE = PF == 0 && B == 1 && !UNIT && TP > 1;
   static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG, UNIT && !POW>;   // the FFT pass keeps shared twiddle sets
 
   // Long tap windows keep their coefficients in LDS (TP x N floats after
   // the FFT planes, shared by the groups of the block) instead of TP x R
   // registers per thread, which would leave one wave per SIMD.
-  static constexpr bool CL = !UNIT && TP >= 16;
+  static constexpr bool CL = !UNIT && (TP >= 16 || fused4096_cl(N, TP));
   static constexpr size_t coef_lds_bytes() { return CL ? (size_t)TP * N * sizeof(float) : 0; }
   static constexpr size_t lds_bytes() { return Fft::lds_bytes() + coef_lds_bytes(); }
 
@@ -606,30 +707,82 @@ struct FusedEngine {
 #pragma unroll
       for (int e = 0; e < R; ++e) { ring[s][e].x = 0.f; ring[s][e].y = 0.f; }
     auto load = [&](v2f (&dst)[R], int vb) {
-      if (vb >= vb_lo && vb < vb_hi) {
+      if constexpr (G == 1 && IT != 0) {
+        // widened input: no branch around the load (a merge of the loaded
+        // bits with the slot's old value would wait for the load here); a
+        // block outside [vb_lo, vb_hi) gets an empty range and reads zeros
+        const bool ok = vb >= vb_lo && vb < vb_hi;
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(block_addr<N, SB>(a, ok ? vb - d : 0), ok ? N * SB : 0);
+        constexpr int aux = kNtLoads ? kAuxNt : 0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const uint32_t so = (uint32_t)(e * W * SB);
+          if constexpr (IT == 1) {
+            dst[e].x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, loff / 2, so, aux));
+          } else {
+            dst[e].x = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, loff / 4, so, aux));
+          }
+        }
+      } else if (vb >= vb_lo && vb < vb_hi) {
         if constexpr (G == 1) {
-          const __amdgpu_buffer_rsrc_t rs = block_rsrc(block_ptr<N>(a, vb - d), N * (int)sizeof(v2f));
+          const __amdgpu_buffer_rsrc_t rs = block_rsrc(block_addr<N, SB>(a, vb - d), N * SB);
+          constexpr int aux = kNtLoads ? kAuxNt : 0;
 #pragma unroll
-          for (int e = 0; e < R; ++e)
-            dst[e] = buf_load<kNtLoads ? kAuxNt : 0>(rs, loff, (uint32_t)(e * W * (int)sizeof(v2f)));
+          for (int e = 0; e < R; ++e) {
+            const uint32_t so = (uint32_t)(e * W * SB);
+            if constexpr (IT == 0) {
+              dst[e] = buf_load<aux>(rs, loff, so);
+            } else if constexpr (IT == 1) {
+              dst[e].x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, loff / 2, so, aux));
+            } else {
+              dst[e].x = __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, loff / 4, so, aux));
+            }
+          }
         } else {
-          const v2f* src = block_ptr<N>(a, vb - d) + j;
+          const char* src = block_addr<N, SB>(a, vb - d);
 #pragma unroll
-          for (int e = 0; e < R; ++e) dst[e] = src[e * W];
+          for (int e = 0; e < R; ++e) {
+            if constexpr (IT == 0) {
+              dst[e] = ((const v2f*)src)[j + e * W];
+            } else if constexpr (IT == 1) {
+              dst[e].x = __builtin_bit_cast(float, ((const uint32_t*)src)[j + e * W]);
+            } else {
+              dst[e].x = __builtin_bit_cast(float, (uint32_t)((const uint16_t*)src)[j + e * W]);
+            }
+          }
+        }
+      }
+    };
+
+    // FP16 / int8 input: a slot first holds the stored bits in .x and is
+    // widened in place at the start of the step that first reads it, so the
+    // wait for its load falls there, PF steps after the load was issued
+    auto widen = [&](v2f (&slot)[R]) {
+      if constexpr (IT != 0) {
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const uint32_t w = __builtin_bit_cast(uint32_t, slot[e].x);
+          slot[e] = IT == 1 ? widen_c16(w) : widen_ci8(w);
         }
       }
     };
 
 #pragma unroll
-    for (int s = 0; s < Q - B; ++s) load(ring[s], m0 + s);
+    for (int s = 0; s < (LATE ? Q : Q - B); ++s) load(ring[s], m0 + s);
+#pragma unroll
+    for (int s = 0; s < TP - 1; ++s) widen(ring[s]);
 
     for (int base = 0; base < niter; base += Q) {
 #pragma unroll
       for (int k = 0; k < Q; k += B) {
         const int it = base + k;
         if (it >= niter) break;
+        if constexpr (!LATE) {
 #pragma unroll
-        for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
+          for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) widen(ring[(k + TP - 1 + b) % Q]);
         v2f v[B][R];
         uint32_t hb = hl;
         if constexpr (CL) asm volatile("" : "+v"(hb));
@@ -653,6 +806,7 @@ struct FusedEngine {
               v[b][e] = acc;
             }
           }
+        if constexpr (LATE) load(ring[k % Q], m0 + it + Q);
         fft.run(v);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -697,7 +851,8 @@ struct FusedEngine {
 
 // Batch form: a wave of tiles of S consecutive spectra covers the batch;
 // group g of block lb owns the tile (lb*G + g).
-template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false>
+template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false,
+          int IT = 0>
 __global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_eu(PPF_SMALL16 && TP >= 16 && N <= 256 ? 2 : 1)))
 ppf_fused_kernel(FusedParams p) {
   constexpr int W = N / R;
@@ -714,7 +869,7 @@ ppf_fused_kernel(FusedParams p) {
   const int brem = p.M - blk_m0;
   const int niter = brem < p.S ? brem : p.S;                   // uniform over the block
 
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW> eng;
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT> eng;
   eng.init(smem, grp, j, p.coef, p.tw, p.d);
   TileArgs a{p.x0, p.x1, p.x1, p.out, p.h0, p.h0, p.pout, p.K};
   eng.run(a, m0, ng, niter);
@@ -723,6 +878,8 @@ ppf_fused_kernel(FusedParams p) {
 // Descriptor form (serving): the tiles are listed in device memory; a
 // persistent grid walks them, G tiles per block at a time. Every wave of a
 // block exits at the same tile index, after the same number of barriers.
+// (Claiming tiles from a per-class atomic counter instead measured slower:
+// 64x against 100x real time sustained at an offered 100x.)
 
 template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT>
 __global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_eu(PPF_SMALL16 && TP >= 16 && N <= 256 ? 2 : 1)))
@@ -769,20 +926,28 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
 #define PPF_PF_FUSED_OVERRIDE 0
 #endif
 
+
 // elements per thread R and groups per block G for the FFT of N points
-constexpr int cfg_R(int N) { return N <= 1024 ? 4 : (N == 2048 ? 8 : (N >= 16384 ? 32 : 16)); }
-constexpr int cfg_RX(int N) { return cfg_R(N) < 16 ? cfg_R(N) : 16; }
-constexpr int cfg_W(int N) { return N / cfg_R(N); }
-constexpr int cfg_G(int N) { return cfg_W(N) >= 256 ? 1 : 256 / cfg_W(N); }
+// (TP = 1: the FFT pass of the two-pass form)
+constexpr int cfg_R(int N, int TP = 1) {
+  return fused4096(N, TP) ? 4 : (N <= 1024 ? 4 : (N == 2048 ? 8 : (N >= 16384 ? 32 : 16)));
+}
+constexpr int cfg_RX(int N, int TP = 1) { return cfg_R(N, TP) < 16 ? cfg_R(N, TP) : 16; }
+constexpr int cfg_W(int N, int TP = 1) { return N / cfg_R(N, TP); }
+constexpr int cfg_G(int N, int TP = 1) { return cfg_W(N, TP) >= 256 ? 1 : 256 / cfg_W(N, TP); }
 #ifndef PPF_PF_16K
 #define PPF_PF_16K 0
 #endif
 constexpr int cfg_PF(int N, int TP) {
+  if (fused4096_late(N, TP)) return 0;
+  if (fused4096_cl(N, TP)) return PPF_F4096_PF;
   return TP == 1 ? (N >= 16384 ? PPF_PF_16K : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
                  : (N >= 2048 || (PPF_SMALL16 && TP >= 16 && N <= 256) ? 2
                                   : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
 }
-constexpr bool cfg_TWG(int N) { return N >= 16384; }
+constexpr bool cfg_TWG(int N, int TP = 1) {
+  return N >= 16384 || fused4096_late(N, TP);
+}
 // spectra per FFT pass (build-time tuning; 4 measured best at N=1024, T=8)
 #ifndef PPF_BATCH_OVERRIDE
 #define PPF_BATCH_OVERRIDE 4
@@ -794,8 +959,8 @@ constexpr int cfg_B(int N, int TP) {
   // with 16 taps the ring already fills the register file
   return PPF_BATCH_OVERRIDE > 1 && TP <= 8 && batch_fits(N, TP, PPF_BATCH_OVERRIDE) ? PPF_BATCH_OVERRIDE : 1;
 }
-constexpr bool cfg_DB(int N, int B) {
-  return 2ull * B * 2 * cfg_G(N) * plane_floats(N, cfg_W(N)) * sizeof(float) <= 80 * 1024;
+constexpr bool cfg_DB(int N, int B, int TP = 1) {
+  return !fused4096_cl(N, TP) && 2ull * B * 2 * cfg_G(N, TP) * plane_floats(N, cfg_W(N, TP)) * sizeof(float) <= 80 * 1024;
 }
 
 struct KernelInfo {
@@ -822,12 +987,12 @@ static int occupancy(const KernelInfo& ki) {
   return occ;
 }
 
-template <int N, int TP, bool UNIT, bool POW = false>
+template <int N, int TP, bool UNIT, bool POW = false, int IT = 0>
 static const KernelInfo& fused_info() {
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>,
-                             (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>::lds_bytes()};
+  constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
+  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>,
+                             (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>::lds_bytes()};
   return ki;
 }
 
@@ -860,10 +1025,10 @@ static BatchArgs sub_batch(const BatchArgs& a, int N, size_t sample_bytes, long 
 
 // POW: the kernel writes |X|^2 summed over K consecutive spectra to pout
 // instead of the spectra (a.M a multiple of K; tiles start at multiples of K).
-template <int N, int TP, bool UNIT, bool POW = false>
+template <int N, int TP, bool UNIT, bool POW = false, int IT = 0>
 static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const float* coef, int T,
                                    hipStream_t st, float* pout = nullptr, int K = 1) {
-  const KernelInfo& ki = fused_info<N, TP, UNIT, POW>();
+  const KernelInfo& ki = fused_info<N, TP, UNIT, POW, IT>();
   static const int occ = occupancy(ki);
   const long long resident_groups = (long long)device_cus() * occ * ki.G;
   long long S = (a.M + resident_groups - 1) / resident_groups;
@@ -885,21 +1050,22 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   p.nblocks = (int)nblocks;
   p.pout = pout;
   p.K = K;
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
-  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW>), dim3((unsigned)nblocks),
+  constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
+  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>), dim3((unsigned)nblocks),
                      dim3(ki.block), ki.lds, st, p);
   return hipGetLastError();
 }
 
-template <int N, int TP, bool UNIT = false, bool POW = false>
+// IT: stored input type (widened to FP32 as it is loaded)
+template <int N, int TP, bool UNIT = false, bool POW = false, int IT = 0>
 static hipError_t fused_launch(const PlanDev& pd, const BatchArgs& a, const float* coef, int T, hipStream_t st,
                                float* pout, int K) {
   const long long step = POW ? kMaxLaunchSpectra / K * K : kMaxLaunchSpectra;
   for (long long s0 = 0; s0 < a.M; s0 += step) {
     const long long k = a.M - s0 < step ? a.M - s0 : step;
-    const hipError_t e = fused_launch_one<N, TP, UNIT, POW>(pd, sub_batch(a, N, 8, s0, k), coef, T, st,
-                                                            POW ? pout + (s0 / K) * N : nullptr, K);
+    const hipError_t e = fused_launch_one<N, TP, UNIT, POW, IT>(pd, sub_batch(a, N, in_bytes(IT), s0, k), coef, T,
+                                                                st, POW ? pout + (s0 / K) * N : nullptr, K);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -911,7 +1077,11 @@ typedef hipError_t (*FusedFn)(const PlanDev&, const BatchArgs&, const float*, in
 // The fused path exists where the tap window of a thread (R channels x TP
 // taps, plus coefficients) fits the register file at useful occupancy.
 constexpr bool fused_ok(int N, int TP) {
-  return TP == 1 || (N <= 1024 && TP <= 16) || (N == 2048 && TP <= 8);
+  return TP == 1 || (N <= 1024 && TP <= 16) || (N == 2048 && TP <= 8) || fused4096(N, TP);
 }
+
+// Fused kernels reading complex FP16 (IT = 1) or int8 (IT = 2) input,
+// built in a translation unit of their own.
+FusedFn fused_fn_widened(int N, int TP, int IT);
 
 }  // namespace ppf

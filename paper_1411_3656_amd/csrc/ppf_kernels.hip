@@ -46,31 +46,6 @@ struct FirParams {
   int d;
 };
 
-// Stored complex input types, widened to FP32 as they are loaded:
-// 0 = complex FP32, 1 = complex FP16, 2 = complex int8 (exact conversions).
-template <int IT>
-__device__ __forceinline__ v2f load_sample(const void* base, long long i) {
-  if constexpr (IT == 0) {
-    return ((const v2f*)base)[i];
-  } else if constexpr (IT == 1) {
-    const uint32_t w = ((const uint32_t*)base)[i];
-    _Float16 re, im;
-    const uint16_t lo = (uint16_t)(w & 0xFFFFu), hi = (uint16_t)(w >> 16);
-    __builtin_memcpy(&re, &lo, 2);
-    __builtin_memcpy(&im, &hi, 2);
-    v2f r;
-    r.x = (float)re;
-    r.y = (float)im;
-    return r;
-  } else {
-    const uint16_t w = ((const uint16_t*)base)[i];
-    v2f r;
-    r.x = (float)(int)(int8_t)(w & 0xFFu);
-    r.y = (float)(int)(int8_t)(w >> 8);
-    return r;
-  }
-}
-
 template <int TP, int PF, int IT>
 __global__ void __launch_bounds__(256) ppf_fir_kernel(FirParams p) {
   constexpr int Q = TP + PF;
@@ -260,7 +235,7 @@ bool fused_available(int N, int TP) { return TP > 1 && fused_fn(N, TP) != nullpt
 bool fft_available(int N) { return fused_fn(N, 1) != nullptr; }
 
 hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
-  FusedFn f = fused_fn(pd.N, pd.TP);
+  FusedFn f = pd.in_type == 0 ? fused_fn(pd.N, pd.TP) : fused_fn_widened(pd.N, pd.TP, pd.in_type);
   if (!f) return hipErrorInvalidValue;
   return f(pd, a, pd.coef, pd.T, st, nullptr, 1);
 }
@@ -356,8 +331,8 @@ hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st) {
 template <int N, int TP, bool UNIT = false>
 static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                                     const float* coef, int T, hipStream_t st) {
-  constexpr int R = cfg_R(N), RX = cfg_RX(N), G = cfg_G(N), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B), TWG = cfg_TWG(N);
+  constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
   using Eng = FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   static const int occ = [&] {

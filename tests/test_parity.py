@@ -95,6 +95,28 @@ def test_more_taps_auto_path(n, taps):
     _small_case(n, taps, ppf.PPF_PATH_AUTO, 157, seed=2000 + n + taps)
 
 
+@pytest.mark.parametrize("taps,m_total", [(8, 2500), (8, 9), (7, 1111), (5, 600), (4, 3000), (3, 257), (2, 600)])
+def test_fused_n4096(taps, m_total):
+    """The fused kernel at N = 4096 (four channels per lane over a
+    1024-thread block; with 5..8 taps the coefficients sit in LDS): several
+    tiles per block and a ragged last tile, every tap count it serves,
+    sampled at tile edges."""
+    n = 4096
+    s_tile = max(-(-m_total // 256), taps)
+    edges = {e for k in range(1, 256) for e in (k * s_tile - 1, k * s_tile) if k * s_tile < m_total}
+    idx = sorted(set(sample_spectra(m_total, taps, every=53)) | set(sorted(edges)[:60]))
+    rng = np.random.default_rng(4096 + taps)
+    h32 = rng.standard_normal(taps * n).astype(np.float32)
+    x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=5000 + taps + m_total)
+    print(f"case fused N=4096 T={taps} M={m_total}", flush=True)
+    got, used = run_gpu(x, h32, n, taps)
+    assert used == ppf.PPF_PATH_FUSED
+    err = rel_err(got[idx], oracle.ppf(x, h32, n, taps, spectra=idx))
+    print(f"fused N=4096 T={taps} M={m_total}: max err / rms = {err:.3e} over {len(idx)} spectra")
+    assert err <= TOL, err
+    assert np.isfinite(got).all()
+
+
 def test_c2_ska_n1024_full():
     """C2 in full: all 131,065 spectra against the oracle (computed in slices
     of spectra so its DFT matrix products stay small)."""

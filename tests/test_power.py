@@ -33,6 +33,8 @@ def _torch():
     (2048, 8, 2, 40, ppf.PPF_PATH_AUTO),
     (1024, 8, 6, 36, ppf.PPF_PATH_TWO_PASS),
     (4096, 16, 8, 32, ppf.PPF_PATH_AUTO),       # two-pass: power in the FFT pass
+    (4096, 8, 5, 600, ppf.PPF_PATH_FUSED),      # fused N=4096: coefficients in LDS
+    (4096, 4, 3, 300, ppf.PPF_PATH_FUSED),      # fused N=4096: coefficients in registers
     (1024, 32, 5, 40, ppf.PPF_PATH_AUTO),
     (16384, 4, 3, 9, ppf.PPF_PATH_AUTO),
 ])

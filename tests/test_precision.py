@@ -81,6 +81,33 @@ def test_reduced_precision_inputs(n, taps, kind, half):
     print(f"  arithmetic err/rms {err:.2e}; end-to-end SNR {snr_db(got, ref64):.1f} dB")
 
 
+@pytest.mark.parametrize("kind", [ppf.PPF_CI8, ppf.PPF_C16], ids=["ci8", "c16"])
+@pytest.mark.parametrize("n,taps,m_total", [(16, 3, 700), (64, 16, 300), (256, 1, 257), (512, 8, 611),
+                                            (1024, 8, 300), (2048, 5, 129), (4096, 8, 300), (4096, 4, 41)])
+def test_widened_fused_and_two_pass(n, taps, m_total, kind):
+    """The fused kernels widen FP16 / int8 samples as they load them; the
+    two-pass form widens in its FIR pass. Both against the same-input
+    oracle at the FP32 bar, over several tiles and a ragged tail."""
+    torch = _torch()
+    x = make_input(kind, (m_total + taps - 1) * n, seed=3 * n + taps + kind)
+    h16, shift, h_exact = stored_coeffs(signals.design_coeffs(n, taps, "hann"), True)
+    idx = sorted(set(range(0, m_total, 11)) | set(range(m_total - 2 * taps, m_total)) | {1, 2})
+    ref = oracle.ppf(x, h_exact, n, taps, spectra=idx)
+    xd = torch.from_numpy(x).cuda()
+    for path in (ppf.PPF_PATH_FUSED, ppf.PPF_PATH_TWO_PASS):
+        print(f"case widened N={n} T={taps} M={m_total} in={kind} path={path}", flush=True)
+        plan = ppf.Plan(n, taps, h16, path, in_type=kind, coeff_shift=shift)
+        assert plan.path == path
+        got = plan.execute(xd)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        plan.close()
+        assert np.isfinite(got).all()
+        err = rel_err(got[idx], ref)
+        print(f"  path {path}: max err/rms {err:.2e}", flush=True)
+        assert err <= TOL, (path, err)
+
+
 def test_int8_stream_split_matches_oracle():
     torch = _torch()
     n, taps = 512, 8

@@ -45,6 +45,7 @@ def push_all(torch, plan, stream, chunks):
     (512, 1, ppf.PPF_PATH_FUSED),
     (1024, 8, ppf.PPF_PATH_TWO_PASS),
     (4096, 16, ppf.PPF_PATH_AUTO),
+    (4096, 8, ppf.PPF_PATH_FUSED),
 ])
 def test_chunk_split_matches_oracle(n, taps, path):
     torch = _torch()
