@@ -238,11 +238,7 @@ struct GroupFft {
   static constexpr int tw_off(int S) { return TWG ? tw_offset_twg(N, R, RX, S) : tw_offset(N, R, RX, S); }
   // stage S reads its twiddles from the table when it starts
   static constexpr bool tw_fetched(int S) { return TWG && S > 0 && (!TWR || ns_at(N, RX, S) > W); }
-  // TWL: the table-twiddle mode reads a copy of the table in LDS (after
-  // the exchange planes) where it fits, at LDS rather than memory latency
-  static constexpr bool TWL = TWG && N <= 4096;
-  static constexpr size_t planes_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
-  static constexpr size_t lds_bytes() { return planes_bytes() + (TWL ? size_t(N) * sizeof(v2f) : 0); }
+  static constexpr size_t lds_bytes() { return size_t(NBUF) * B * 2 * G * PL * sizeof(float); }
   static constexpr bool IL = lds_b64(N);             // interleaved (re, im) elements
   // XL (N >= 4096 with a multiple of 512 threads per group: 16 or 32
   // elements per thread at N >= 8192, 4 over 1024 threads in the fused
@@ -259,7 +255,6 @@ struct GroupFft {
   int grp, j;
   int par;         // buffer of the next exchange (double-buffered mode)
   const v2f* tw;   // twiddle table (global)
-  uint32_t twl;    // TWL: LDS byte address of the table's copy
   v2f twr[NTW];
   int rb;          // XL: swizzled element j (the reads of every stage add e*W)
   int wb[L];       // XL: swizzled first write element of each stage
@@ -293,12 +288,6 @@ struct GroupFft {
 
   __device__ __forceinline__ void init(float* smem, int grp_, int j_, const v2f* tw_) {
     lds = smem; grp = grp_; j = j_; par = 0; tw = tw_;
-    if constexpr (TWL) {
-      v2f* t = (v2f*)((char*)smem + planes_bytes());
-      for (int i = threadIdx.x; i < N; i += blockDim.x) t[i] = tw_[i];
-      __syncthreads();
-      twl = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) v2f*)t;
-    }
     if constexpr (XL) {
       rb = swz64(j);
 #pragma unroll
@@ -326,22 +315,11 @@ struct GroupFft {
     constexpr int r = radix_at(N, RX, S), Ns = ns_at(N, RX, S);
     int z;
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-    // TWL: the LDS addresses are formed here from an opaque copy of j, so
-    // no per-stage address stays live across the spectrum loop
-    int jj = j;
-    if constexpr (TWL) asm volatile("" : "+v"(jj));
 #pragma unroll
     for (int ib = 0; ib < stage_sets<S>(); ++ib) {
-      const int k = (jj + ib * W) % Ns;
+      const int k = (j + ib * W) % Ns;
 #pragma unroll
-      for (int q = 1; q < r; ++q) {
-        if constexpr (TWL) {
-          tl[ib * (r - 1) + q - 1] = *(const __attribute__((address_space(3))) v2f*)(uintptr_t)(
-              twl + (uint32_t)((k * q * (N / (Ns * r)) + z) * (int)sizeof(v2f)));
-        } else {
-          tl[ib * (r - 1) + q - 1] = tw[k * q * (N / (Ns * r)) + z];
-        }
-      }
+      for (int q = 1; q < r; ++q) tl[ib * (r - 1) + q - 1] = tw[k * q * (N / (Ns * r)) + z];
     }
   }
 
@@ -598,26 +576,12 @@ __device__ __forceinline__ v2f load_sample(const void* base, long long i) {
 #define PPF_FUSED_4096 1
 #endif
 constexpr bool fused4096(int N, int TP) { return PPF_FUSED_4096 && N == 4096 && TP > 1 && TP <= 8; }
-// With 5..8 taps a ring of TP + 2 blocks, the coefficients (8 x 4 per
+// With 5..8 taps a ring of 8 + 2 blocks, the coefficients (8 x 4 per
 // lane) and the twiddles exceed the 128 registers of a lane at 4 waves per
-// SIMD: the ring holds exactly the tap window, the block the next step
-// needs is loaded into the slot the FIR has just consumed (so the load runs
-// during the FFT), and the twiddles are read per stage from a copy of the
-// table in LDS. (Coefficients in LDS instead measured 26% of HBM peak at
-// T = 8 against 39% for this.)
-#ifndef PPF_LATE_MIN_TP
-#define PPF_LATE_MIN_TP 8
-#endif
-#ifndef PPF_F4096_T8
-#define PPF_F4096_T8 0
-#endif
-#ifndef PPF_F4096_PF
-#define PPF_F4096_PF 1
-#endif
-constexpr bool fused4096_late(int N, int TP) {
-  return PPF_F4096_T8 == 0 && fused4096(N, TP) && TP >= PPF_LATE_MIN_TP;
-}
-constexpr bool fused4096_cl(int N, int TP) { return PPF_F4096_T8 == 1 && fused4096(N, TP) && TP == 8; }
+// SIMD: the coefficients go to LDS (128 KiB beside one 32 KiB exchange
+// buffer, so the exchanges are single-buffered) and the ring prefetches
+// one block.
+constexpr bool fused4096_cl(int N, int TP) { return fused4096(N, TP) && TP == 8; }
 
 // Per-block engine of the fused kernel: coefficients, twiddles and lane
 // offsets are loaded once and reused by every tile the block processes.
@@ -637,10 +601,6 @@ struct FusedEngine {
   static_assert(!UNIT || IT == 0, "the FFT pass reads FP32 presums");
   static constexpr int Q = TP + PF;
   static_assert(Q % B == 0 && Q >= TP + B - 1, "ring size");
-  // LATE: the ring is the tap window alone (no prefetch slots); each step
-  // loads the block the next step needs into the slot its FIR has just
-  // read, after the FIR and before the FFT, which covers the load.
-  static constexpr bool LATE = PF == 0 && B == 1 && !UNIT && TP > 1;
   static_assert(!UNIT || TP == 1, "unit coefficients are a single tap");
   using Fft = GroupFft<N, R, RX, G, B, DB, TWG, UNIT && !POW>;   // the FFT pass keeps shared twiddle sets
 
@@ -768,7 +728,7 @@ struct FusedEngine {
     };
 
 #pragma unroll
-    for (int s = 0; s < (LATE ? Q : Q - B); ++s) load(ring[s], m0 + s);
+    for (int s = 0; s < Q - B; ++s) load(ring[s], m0 + s);
 #pragma unroll
     for (int s = 0; s < TP - 1; ++s) widen(ring[s]);
 
@@ -777,10 +737,8 @@ struct FusedEngine {
       for (int k = 0; k < Q; k += B) {
         const int it = base + k;
         if (it >= niter) break;
-        if constexpr (!LATE) {
 #pragma unroll
-          for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
-        }
+        for (int b = 0; b < B; ++b) load(ring[(k + Q - B + b) % Q], m0 + it + Q - B + b);
 #pragma unroll
         for (int b = 0; b < B; ++b) widen(ring[(k + TP - 1 + b) % Q]);
         v2f v[B][R];
@@ -806,7 +764,6 @@ struct FusedEngine {
               v[b][e] = acc;
             }
           }
-        if constexpr (LATE) load(ring[k % Q], m0 + it + Q);
         fft.run(v);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -886,7 +843,6 @@ __global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_e
 ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* coef, const v2f* tw, int d) {
   constexpr int W = N / R;
   extern __shared__ float smem[];
-  __shared__ int s_count[G];
   const int tid = threadIdx.x;
   const int grp = (G == 1) ? 0 : tid / W;
   const int j = (G == 1) ? tid : tid % W;
@@ -906,6 +862,7 @@ ppf_fused_desc_kernel(const DescClass* cls, const TileDesc* tiles, const float* 
     }
     int niter = count;
     if constexpr (G > 1) {
+      __shared__ int s_count[G];     // only where G > 1: the G = 1 kernels may use all of LDS
       if (j == 0) s_count[grp] = count;
       __syncthreads();
       niter = 0;
@@ -939,15 +896,12 @@ constexpr int cfg_G(int N, int TP = 1) { return cfg_W(N, TP) >= 256 ? 1 : 256 / 
 #define PPF_PF_16K 0
 #endif
 constexpr int cfg_PF(int N, int TP) {
-  if (fused4096_late(N, TP)) return 0;
-  if (fused4096_cl(N, TP)) return PPF_F4096_PF;
+  if (fused4096_cl(N, TP)) return 1;
   return TP == 1 ? (N >= 16384 ? PPF_PF_16K : (N >= 4096 ? 1 : (N >= 2048 ? 2 : 3)))
                  : (N >= 2048 || (PPF_SMALL16 && TP >= 16 && N <= 256) ? 2
                                   : (PPF_PF_FUSED_OVERRIDE > 0 ? PPF_PF_FUSED_OVERRIDE : 4));
 }
-constexpr bool cfg_TWG(int N, int TP = 1) {
-  return N >= 16384 || fused4096_late(N, TP);
-}
+constexpr bool cfg_TWG(int N) { return N >= 16384; }
 // spectra per FFT pass (build-time tuning; 4 measured best at N=1024, T=8)
 #ifndef PPF_BATCH_OVERRIDE
 #define PPF_BATCH_OVERRIDE 4
@@ -990,7 +944,7 @@ static int occupancy(const KernelInfo& ki) {
 template <int N, int TP, bool UNIT, bool POW = false, int IT = 0>
 static const KernelInfo& fused_info() {
   constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N);
   static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>,
                              (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>::lds_bytes()};
   return ki;
@@ -1051,7 +1005,7 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   p.pout = pout;
   p.K = K;
   constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N);
   hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>), dim3((unsigned)nblocks),
                      dim3(ki.block), ki.lds, st, p);
   return hipGetLastError();

@@ -332,7 +332,7 @@ template <int N, int TP, bool UNIT = false>
 static hipError_t fused_desc_launch(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,
                                     const float* coef, int T, hipStream_t st) {
   constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N, TP);
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N);
   using Eng = FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   auto kern = &ppf_fused_desc_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT>;
   static const int occ = [&] {
