@@ -295,7 +295,10 @@ def main() -> int:
         m_total = n_samples // n - taps + 1
         h64 = signals.design_coeffs(n, taps, "hamming")
         h16, shift = signals.coeffs_fp16(h64)
-        for kind, name, sb, seed in ((ppf.PPF_CI8, "int8", 2, 5), (ppf.PPF_C16, "fp16", 4, 6)):
+        for kind, name, sb, seed, fft in ((ppf.PPF_CI8, "int8", 2, 5, ppf.PPF_FFT_F32),
+                                          (ppf.PPF_C16, "fp16", 4, 6, ppf.PPF_FFT_F32),
+                                          (ppf.PPF_CI8, "int8", 2, 5, ppf.PPF_FFT_MFMA_F16),
+                                          (ppf.PPF_C16, "fp16", 4, 6, ppf.PPF_FFT_MFMA_F16)):
             if kind == ppf.PPF_CI8:
                 x = signals.int8_input(n_samples, seed=signals.SEED_BASE + seed, sigma=16.0)
             else:
@@ -303,12 +306,15 @@ def main() -> int:
             x_dev = torch.from_numpy(x).cuda()
             del x
             ms, used = run_point(torch, n, taps, m_total, x_dev, h16, args.steps, args.warmup, path,
-                                 in_type=kind, coeff_shift=shift)
-            rec = line(f"ska_lfaa_n1024_t8_2p27_{name}_in", n, taps, m_total, ms, used, args.steps, args.warmup)
+                                 in_type=kind, coeff_shift=shift, fft_mode=fft)
+            mc = fft == ppf.PPF_FFT_MFMA_F16
+            rec = line(f"ska_lfaa_n1024_t8_2p27_{name}_in" + ("_mfma" if mc else ""), n, taps, m_total, ms, used,
+                       args.steps, args.warmup)
+            rec["config"]["fft"] = "mfma_f16_radix4_16_16" if mc else "f32"
             in_b = metrics.input_bytes(n, m_total, sb)
             rec["value"] = round(in_b / (ms * 1e-3) / 1e9, 3)
             rec["realtime_multiple"] = round(metrics.realtime_multiple(rec["value"] * 1e9), 2)
-            rec["dtype"] = f"{'ci8' if sb == 2 else 'c16'}_in/f16_coef/f32"
+            rec["dtype"] = f"{'ci8' if sb == 2 else 'c16'}_in/f16_coef/f32" + ("_fir/f16_mfma_f32_acc" if mc else "")
             alg = metrics.algorithmic_bytes(n, taps, m_total, in_bytes=sb, out_bytes=8, coeff_bytes=2)
             rec["roofline"].update({"achieved": round(alg / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": alg})
             rec["roofline"]["frac"] = round(rec["roofline"]["achieved"] / rec["roofline"]["peak"], 4)

@@ -128,11 +128,13 @@ ppf_plan_t ppf_plan(int n_channels, int taps, const float* coeffs);
  *         the FIR accumulates in FP32. Output is always C32.
  * fft_mode: PPF_FFT_F32 or PPF_FFT_MFMA_F16 (PPF_ERR_UNSUPPORTED where the
  *         MFMA stages are not built for N). The matrix-core mode is built
- *         for N = 4096 = 16^3, T <= 16, PPF_R16 coefficients and PPF_CI8 or
- *         PPF_C16 input; the samples enter the FP16 stages scaled by a power
- *         of two chosen so that no stage input can overflow for any input
- *         value of that type (|x| <= 128 for int8, 65504 for FP16). Any
- *         other combination is PPF_ERR_UNSUPPORTED.
+ *         for N = 4096 = 16^3 (three radix-16 stages), N = 1024 = 4 * 16^2
+ *         (a radix-4 stage in FP32, then two radix-16 stages) and N = 256 =
+ *         16^2, T <= 16, PPF_R16 coefficients and PPF_CI8 or PPF_C16 input;
+ *         the samples enter the FP16 stages scaled by a power of two chosen
+ *         so that no stage input can overflow for any input value of that
+ *         type (|x| <= 128 for int8, 65504 for FP16). Any other combination
+ *         is PPF_ERR_UNSUPPORTED.
  */
 ppf_plan_t ppf_plan_ex(int n_channels, int taps, const void* coeffs, int coeff_type,
                        int coeff_shift, int in_type, int fft_mode);

@@ -175,10 +175,12 @@ struct ppf_plan_s {
   }
   ppf::MfmaDev mfma() const {
     ppf::MfmaDev m;
+    m.N = N;
+    m.tq = ppf::mfma_tap_slots(N, T);
     m.coef16 = d_coef16;
     m.tw = d_tw;
     m.w256 = d_w256;
-    m.d = 16 - T;
+    m.d = m.tq - T;
     m.in_type = in_type == PPF_C16 ? 1 : 2;
     m.in_scale = std::ldexp(1.0f, -mfma_e1);
     m.out_scale = std::ldexp(1.0f, mfma_e1 - coeff_shift);
@@ -414,7 +416,7 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   if (fft_mode == PPF_FFT_MFMA_F16) {
     if (!ppf::mfma_available(N, taps) || (in_type != PPF_CI8 && in_type != PPF_C16) || coeff_type != PPF_R16) {
       fail(PPF_ERR_UNSUPPORTED,
-           "fft_mode=MFMA_F16 takes N=4096, taps <= 16, complex int8 or FP16 input and FP16 coefficients "
+           "fft_mode=MFMA_F16 takes N=256, 1024 or 4096, taps <= 16, complex int8 or FP16 input and FP16 coefficients "
            "(got N=%d taps=%d in_type=%d coeff_type=%d)", N, taps, in_type, coeff_type);
       return nullptr;
     }
@@ -457,13 +459,17 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   if ((e = ppf::launch_twiddles(p->d_tw, N, nullptr)) != hipSuccess) goto hip_fail;
   if (fft_mode == PPF_FFT_MFMA_F16) {
     // FP16 coefficients in the kernel's lane order, and the sample scale:
-    // the largest FP16 stage input is at most X * 256 * S * 2^-e1 with
+    // the largest FP16 stage input is at most X * g * S * 2^-e1 with
     // S = max over channels of sum_t |h16[t][c]|, X the largest input
     // magnitude (128 for int8, 65504 for FP16: any finite FP16 input) and
-    // two radix-16 stages of growth <= 16 each; e1 keeps it below 60000.
+    // g the growth before the last FP16 stage input: 256 at N = 4096 (two
+    // radix-16 stages), 64 at N = 1024 (radix 4, then 16), 16 at N = 256;
+    // e1 keeps it below 60000.
     const uint16_t* h16 = (const uint16_t*)coeffs;
-    std::vector<uint16_t> lane(ppf::mfma_coef_bytes() / 2);
-    ppf::mfma_coef_layout(h16, taps, lane.data());
+    const int tq = ppf::mfma_tap_slots(N, taps);
+    std::vector<uint16_t> lane(ppf::mfma_coef_bytes(N, tq) / 2);
+    ppf::mfma_coef_layout(N, tq, h16, taps, lane.data());
+    const double growth = N == 4096 ? 256.0 : (N == 1024 ? 64.0 : 16.0);
     double smax = 0.0;
     for (int c = 0; c < N; ++c) {
       double sc = 0.0;
@@ -477,7 +483,7 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
     // [-12, 15]. Among the admissible values the smallest (the most FP16
     // headroom used) is taken.
     const double xmax = in_type == PPF_CI8 ? 128.0 : 65504.0;
-    const int e1_range = smax > 0.0 ? (int)std::ceil(std::log2(xmax * 256.0 * smax / 60000.0)) : -8;
+    const int e1_range = smax > 0.0 ? (int)std::ceil(std::log2(xmax * growth * smax / 60000.0)) : -8;
     int e1 = e1_range;
     if (e1 < -8) e1 = -8;
     if (e1 < coeff_shift - 12) e1 = coeff_shift - 12;

@@ -103,17 +103,20 @@ hipError_t launch_fft_power(const PlanDev& pd, const void* in, float* pout, long
 // Reduced-precision fused kernel with matrix-core DFT stages (N = 4096,
 // complex int8 or FP16 input, FP16 coefficients).
 struct MfmaDev {
-  const void* coef16;  // 16 tap slots x 4096 FP16 coefficients in lane order
-  const void* tw;      // 4096 complex FP32 twiddles
+  int N;               // 4096, 1024 or 256
+  int tq;              // tap slots of the kernel (16; 8 or 16 below N = 4096)
+  const void* coef16;  // tq tap slots x N FP16 coefficients in lane order
+  const void* tw;      // N complex FP32 twiddles
   const void* w256;    // 256 complex FP16 values exp(-2 pi i k/256)
-  int d;               // leading zero tap slots (16 - T)
+  int d;               // leading zero tap slots (tq - T)
   int in_type;         // 2 complex int8, 1 complex FP16
   float in_scale;      // 2^-e1: on the int8 samples (exact in FP16), or on the FIR's FP32 sums
   float out_scale;     // 2^(e1 - coeff_shift), folded exactly into the FP16 stage-3 matrix
 };
 bool mfma_available(int N, int TP);
-size_t mfma_coef_bytes();
-void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst);
+int mfma_tap_slots(int N, int T);
+size_t mfma_coef_bytes(int N, int TQ);
+void mfma_coef_layout(int N, int TQ, const uint16_t* h16, int T, uint16_t* dst);
 hipError_t launch_w256(void* table, hipStream_t st);
 
 // Prototype-filter design (plan time): v (L doubles) and h (L floats) and

@@ -386,6 +386,308 @@ __global__ void __launch_bounds__(kThreads) ppf_mfma_kernel(MfmaParams p) {
   eng.run();
 }
 
+// ---------------------------------------------------------------------------
+// N = 256 = 16^2 and N = 1024 = 16^2 * 4
+//
+// With c = a + 16 b + 256 p (p < 4 at N = 1024, absent at N = 256) and
+// k = k1 + 4 k2 + 64 k3 at N = 1024 the exponent c k splits so that
+//   X = sum_a W16^(a k3) W1024^(a (k1 + 4 k2)) sum_b W64^(b (k1 + 4 k2)) sum_p W4^(p k1) u[c]:
+// a radix-4 DFT over p in FP32 registers (the four channels a lane holds),
+// a 16-point transform over b whose matrix W64^(b (4 k2 + k1)) carries the
+// inter-stage twiddle (k1 is fixed per wave), one FP32 twiddle, and a
+// plain 16-point DFT over a; the last two on the matrix cores. At N = 256
+// (c = a + 16 b, k = k1 + 16 k2): a 16-point DFT over b, the FP32 twiddle
+// W256^(a k1), a 16-point DFT over a.
+//
+// A spectrum takes N / 256 waves; a 1024-thread workgroup holds 16 / (N /
+// 256) groups, each with its own tile of spectra (all groups of a block
+// step together). Lane (w, j, h) of a group owns channels
+//   N = 1024: j + 16 h + 64 w + 256 e  (a = j, b = h + 4 w, p = e),
+//   N = 256:  j + 64 h + 16 e          (a = j, b = 4 h + e),
+// e < 4, so the FIR output is the stage-1 input without an exchange. The
+// ring has TQ slots (8 or 16 taps). Stage outputs go through swizzled LDS
+// buffers (per group) with every half-wave's 4-byte writes on distinct
+// banks and 16-byte reads of whole groups.
+// ---------------------------------------------------------------------------
+
+template <int N, int TQ, int PF, int AUX, int IT, bool POW>
+struct MfmaSmall {
+  static constexpr int GW = N / 256;           // waves per spectrum
+  static constexpr int GL = 64 * GW;           // lanes per group
+  static constexpr int G = kThreads / GL;      // groups per workgroup
+  static constexpr int SB = IT == kInI8 ? 2 : 4;
+  static constexpr int CoefBytes = TQ * N * 2;
+  static constexpr int XB = N * 4;             // one FP16 complex exchange buffer
+  static constexpr int NX = N == 1024 ? 2 : 1;
+  static constexpr int LdsBytes = CoefBytes + G * NX * XB;
+  static constexpr int ESTRIDE = N == 1024 ? 256 : 16;   // channel step of element e
+  static_assert(N == 256 || N == 1024, "built for N = 256 and 1024");
+  static_assert(TQ % PF == 0, "prefetch depth divides the ring");
+
+  const MfmaParams& p;
+  uint8_t* lds;
+  int tid, grp, lg, w, j, h;
+  int m0, ng, niter;
+  int vb_lo, vb_hi;
+  uint32_t in_off, out_off, cf;
+  uint32_t xw, xr, yw, yr;   // exchange byte offsets (r = 0 writes, reads)
+  h8 a2, a3;                 // A operands of the matrix-core stages
+  v2f twv[4];                // FP32 twiddles of this lane's stage outputs
+  h2 sc, bias;
+  float pw[4] = {0.f, 0.f, 0.f, 0.f};
+
+  __device__ __forceinline__ MfmaSmall(const MfmaParams& p_, uint8_t* lds_) : p(p_), lds(lds_) {}
+
+  // X (N = 1024, stage 1 -> 2): word 256 k1 + 16 a + b, bits 2-3 ^= bits 6-7
+  static __device__ __forceinline__ constexpr int swx(int x) { return x ^ (((x >> 6) & 3) << 2); }
+  // Y: N = 1024 word 16 kappa + a (kappa = k1 + 4 k2), bits 4-5 ^= bits 8-9;
+  //    N = 256 word 16 k1 + a, bits 4-5 ^= bits 6-7
+  static __device__ __forceinline__ constexpr int swy(int x) {
+    return N == 1024 ? x ^ (((x >> 8) & 3) << 4) : x ^ (((x >> 6) & 3) << 4);
+  }
+
+  __device__ __forceinline__ const uint8_t* block_ptr(int rb) const {
+    return rb < p.h0 ? (const uint8_t*)p.x0 + (size_t)rb * N * SB
+                     : (const uint8_t*)p.x1 + (size_t)(rb - p.h0) * N * SB;
+  }
+  __device__ __forceinline__ void load(uint32_t (&dst)[4], int vb) const {
+    const bool in = vb >= vb_lo && vb < vb_hi;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(in ? block_ptr(vb - p.d) : p.x1, in ? N * SB : 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (IT == kInI8) dst[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, in_off, ESTRIDE * SB * e, AUX);
+      else dst[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, in_off, ESTRIDE * SB * e, AUX);
+    }
+  }
+  __device__ __forceinline__ void widen(const uint32_t (&raw)[4], uint32_t (&slot)[4]) const {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (IT == kInI8) {
+        slot[e] = widen1(raw[e], sc, bias);
+      } else {
+        // FP16 as stored; an explicit move gives the slot a definition of
+        // its own at this step (letting the load's register be the slot
+        // measured 70+ VGPRs of spills)
+        asm volatile("v_mov_b32 %0, %1" : "=v"(slot[e]) : "v"(raw[e]));
+      }
+    }
+  }
+
+  __device__ __forceinline__ void init(int lb) {
+    tid = threadIdx.x;
+    grp = tid / GL;
+    lg = tid % GL;
+    w = lg >> 6;
+    j = tid & 15;
+    h = (tid >> 4) & 3;
+    const int blk_m0 = lb * G * p.S;
+    const int brem = p.M - blk_m0;
+    niter = brem < p.S ? brem : p.S;          // the block's first group has the most
+    m0 = blk_m0 + grp * p.S;
+    const int rem = p.M - m0;
+    ng = rem <= 0 ? 0 : (rem < p.S ? rem : p.S);
+    vb_lo = m0 > p.d ? m0 : p.d;
+    vb_hi = ng > 0 ? m0 + ng + TQ - 1 : m0;
+    const int c0 = N == 1024 ? j + 16 * h + 64 * w : j + 64 * h;
+    in_off = (uint32_t)c0 * (uint32_t)SB;
+    cf = (uint32_t)lg * 8u;
+    const uint32_t xg = CoefBytes + grp * NX * XB;
+    if constexpr (N == 1024) {
+      out_off = (uint32_t)(16 * w + j + 256 * h) * 8u;
+      xw = xg + swx(16 * j + 4 * w + h) * 4;                  // + 1024 r (k1 = r: above the swizzle)
+      xr = xg + swx(256 * w + 16 * j + 4 * h) * 4;            // k1 = w, a = j, b = 4h..4h+3
+      yw = xg + XB + swy(16 * w + 256 * h + j) * 4;           // + 256 r bytes (bits 6-7: not swizzled)
+      yr = xg + XB + swy(256 * w + 16 * j + 4 * h) * 4;       // kappa = 16 w + j, a = 4h..4h+3
+    } else {
+      out_off = (uint32_t)(j + 64 * h) * 8u;
+      yw = xg + (64 * h + j) * 4;                             // word 64 h + 16 (r ^ h) + j
+      yr = xg + swy(16 * j + 4 * h) * 4;                      // k1 = j, a = 4h..4h+3
+    }
+    const _Float16 s16 = (_Float16)p.in_scale;
+    sc = h2{s16, s16};
+    const _Float16 b16 = (_Float16)(-1152.0f * p.in_scale);
+    bias = h2{b16, b16};
+
+    for (int i = tid; i < CoefBytes / 16; i += kThreads) ((uint4*)lds)[i] = p.coef[i];
+
+    // A operands (real-part row j; inputs point 4h+e, re/im interleaved)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int q = 4 * h + e;
+      const h2 wa = __builtin_bit_cast(h2, p.w256[N == 1024 ? (4 * q * (4 * j + w)) & 255 : (16 * q * j) & 255]);
+      const h2 w3 = __builtin_bit_cast(h2, p.w256[(16 * q * j) & 255]);
+      a2[2 * e] = wa.x;                       // N = 1024: W64^(b (4 k2 + k1)); N = 256: W16^(b k1)
+      a2[2 * e + 1] = -wa.y;
+      a3[2 * e] = (_Float16)((float)w3.x * p.out_scale);
+      a3[2 * e + 1] = (_Float16)(-(float)w3.y * p.out_scale);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      twv[r] = N == 1024 ? p.tw[(j * (w + 4 * (4 * h + r))) & (N - 1)] : p.tw[(j * (4 * h + r)) & (N - 1)];
+  }
+
+  __device__ __forceinline__ void dft16(const h8& a, const h8& b, f4& dre, f4& dim) const {
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    dre = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, z, 0, 0, 0);
+    const uint4 bu = __builtin_bit_cast(uint4, b);
+    uint4 bq;
+    const uint32_t one_neg = 0xBC003C00u;   // FP16 (1.0, -1.0)
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.x) : "v"(bu.x), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.y) : "v"(bu.y), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.z) : "v"(bu.z), "s"(one_neg));
+    asm("v_pk_mul_f16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(bq.w) : "v"(bu.w), "s"(one_neg));
+    dim = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, bq), z, 0, 0, 0);
+  }
+
+  // exchange within a wave (N = 256): LDS operations of one wave complete
+  // in order; the fences keep the compiler from moving them across
+  __device__ __forceinline__ static void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+
+  __device__ __forceinline__ void run() {
+    uint32_t ring[TQ][4];
+    uint32_t stage[PF][4];
+#pragma unroll
+    for (int s = 0; s < TQ; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ring[s][e] = 0u;
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) stage[s][e] = 0u;
+#pragma unroll
+    for (int s = 0; s < TQ - 1; ++s) {
+      uint32_t raw[4];
+      load(raw, m0 + s);
+      widen(raw, ring[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < PF; ++s) load(stage[s], m0 + TQ - 1 + s);
+    __syncthreads();   // coefficients in LDS
+
+    // every group runs the block's step count (barriers); steps past its
+    // own spectra run on zero input and store into an empty range
+    for (int base = 0; base < niter; base += TQ) {
+#pragma unroll
+      for (int k = 0; k < TQ; ++k) {
+        const int it = base + k;
+        widen(stage[k % PF], ring[(k + TQ - 1) % TQ]);
+        load(stage[k % PF], m0 + it + TQ - 1 + PF);
+#pragma unroll
+        for (int s = 0; s < TQ; ++s)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(ring[s][e]));
+        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < TQ; ++t) {
+          const h4 hv = *(const h4*)(lds + t * (GL * 8) + cf);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const h2 xv = __builtin_bit_cast(h2, ring[(k + t) % TQ][e]);
+            ar[e] = fmaf((float)hv[e], (float)xv.x, ar[e]);
+            ai[e] = fmaf((float)hv[e], (float)xv.y, ai[e]);
+          }
+        }
+        if constexpr (IT == kInF16) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            ar[e] *= p.in_scale;
+            ai[e] *= p.in_scale;
+          }
+        }
+        f4 dre, dim;
+        if constexpr (N == 1024) {
+          // stage 1: radix-4 over p = e in FP32 (y_k1 = sum_p (-i)^(p k1) u_p)
+          const float t0r = ar[0] + ar[2], t0i = ai[0] + ai[2];
+          const float t1r = ar[0] - ar[2], t1i = ai[0] - ai[2];
+          const float t2r = ar[1] + ar[3], t2i = ai[1] + ai[3];
+          const float t3r = ar[1] - ar[3], t3i = ai[1] - ai[3];
+          uint32_t* dx = (uint32_t*)(lds + xw);
+          asm volatile("" : "+v"(dx));
+          dx[0] = pack_h2(t0r + t2r, t0i + t2i);         // k1 = 0
+          dx[256] = pack_h2(t1r + t3i, t1i - t3r);       // k1 = 1: t1 - i t3
+          dx[512] = pack_h2(t0r - t2r, t0i - t2i);       // k1 = 2
+          dx[768] = pack_h2(t1r - t3i, t1i + t3r);       // k1 = 3: t1 + i t3
+          __syncthreads();
+          dft16(a2, __builtin_bit_cast(h8, *(const uint4*)(lds + xr)), dre, dim);   // over b
+          // W1024^(a (k1 + 4 k2)) in FP32, to the stage-3 layout
+          uint32_t* dy = (uint32_t*)(lds + yw);
+          asm volatile("" : "+v"(dy));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float yr_ = fmaf(dre[r], twv[r].x, -dim[r] * twv[r].y);
+            const float yi_ = fmaf(dre[r], twv[r].y, dim[r] * twv[r].x);
+            dy[64 * r] = pack_h2(yr_, yi_);
+          }
+          __syncthreads();
+          dft16(a3, __builtin_bit_cast(h8, *(const uint4*)(lds + yr)), dre, dim);   // over a
+        } else {
+          h8 b;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            b[2 * e] = (_Float16)ar[e];
+            b[2 * e + 1] = (_Float16)ai[e];
+          }
+          dft16(a2, b, dre, dim);                                  // over b
+          uint32_t yb = yw;
+          int hh = h;
+          asm volatile("" : "+v"(yb), "+v"(hh));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float yr_ = fmaf(dre[r], twv[r].x, -dim[r] * twv[r].y);
+            const float yi_ = fmaf(dre[r], twv[r].y, dim[r] * twv[r].x);
+            *(uint32_t*)(lds + yb + ((r ^ hh) << 6)) = pack_h2(yr_, yi_);   // 16 (r ^ h) words
+          }
+          wave_sync();
+          dft16(a3, __builtin_bit_cast(h8, *(const uint4*)(lds + yr)), dre, dim);   // over a
+          wave_sync();                                             // reads done before the next writes
+        }
+        // bins: N = 1024 k = 16 w + j + 256 h + 64 r; N = 256 k = j + 64 h + 16 r
+        constexpr uint32_t RSTEP = N == 1024 ? 64u : 16u;
+        if constexpr (POW) {
+          if (it < ng) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pw[r] += fmaf(dre[r], dre[r], dim[r] * dim[r]);
+            if ((m0 + it + 1) % p.K == 0) {
+              const long long q = (long long)(m0 + it) / p.K;
+              const __amdgpu_buffer_rsrc_t rs = rsrc(p.pout + q * N, N * 4);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw[r]), rs, out_off / 2,
+                                                      RSTEP * 4u * r, kAuxNt);
+                pw[r] = 0.f;
+              }
+            }
+          }
+        } else {
+          const __amdgpu_buffer_rsrc_t rs = rsrc(p.out + (size_t)(m0 + it) * N, it < ng ? N * 8 : 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            v2f o;
+            o.x = dre[r];
+            o.y = dim[r];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, o), rs, out_off, RSTEP * 8u * r, kAuxNt);
+          }
+        }
+      }
+    }
+  }
+};
+
+template <int N, int TQ, int PF, int AUX, int IT, bool POW>
+__global__ void __launch_bounds__(kThreads) ppf_mfma_small_kernel(MfmaParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds_small[];
+  using E = MfmaSmall<N, TQ, PF, AUX, IT, POW>;
+  const int lb = xcd_tile(blockIdx.x, p.nblocks);
+  if (lb * E::G * p.S >= p.M) return;    // whole block idle
+  E eng(p, lds_small);
+  eng.init(lb);
+  eng.run();
+}
+
 __global__ void ppf_w256_kernel(uint32_t* t) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < 256) {
@@ -407,6 +709,10 @@ __global__ void ppf_w256_kernel(uint32_t* t) {
 using MfmaKernel = void (*)(MfmaParams);
 template <int IT, bool POW>
 constexpr MfmaKernel mfma_kernel() { return ppf_mfma_kernel<PPF_MFMA_PF, PPF_MFMA_NT ? kAuxNt : 0, IT, POW>; }
+template <int N, int TQ, int IT, bool POW>
+constexpr MfmaKernel mfma_small_kernel() {
+  return ppf_mfma_small_kernel<N, TQ, PPF_MFMA_PF, PPF_MFMA_NT ? kAuxNt : 0, IT, POW>;
+}
 
 int cu_count() {
   static int n = 0;
@@ -420,20 +726,27 @@ int cu_count() {
 
 }  // namespace
 
-bool mfma_available(int N, int TP) { return N == kN && TP <= kTaps; }
+bool mfma_available(int N, int TP) { return (N == kN || N == 1024 || N == 256) && TP <= kTaps; }
 
-size_t mfma_coef_bytes() { return (size_t)kCoefBytes; }
+int mfma_tap_slots(int N, int T) { return N == kN ? kTaps : (T <= 8 ? 8 : 16); }
 
-// FP16 coefficients h16[t*N + c] (T taps) -> lane-order table of 16 slots,
-// the first 16-T zero: slot t, thread tid, element e holds the coefficient
-// of channel 16*(tid/64) + tid%16 + 1024*((tid/16)%4) + 256*e.
-void mfma_coef_layout(const uint16_t* h16, int T, uint16_t* dst) {
-  const int d = kTaps - T;
-  for (int t = 0; t < kTaps; ++t)
-    for (int tid = 0; tid < kThreads; ++tid)
+size_t mfma_coef_bytes(int N, int TQ) { return (size_t)TQ * N * 2; }
+
+// FP16 coefficients h16[t*N + c] (T taps) -> lane-order table of TQ slots,
+// the first TQ-T zero: slot t, lane l (of a group of N/4), element e holds
+// the coefficient of the channel that lane loads:
+//   N = 4096: 16*(l/64) + l%16 + 1024*((l/16)%4) + 256*e
+//   N = 1024: l%16 + 16*((l/16)%4) + 64*(l/64) + 256*e
+//   N = 256:  l%16 + 64*((l/16)%4) + 16*e
+void mfma_coef_layout(int N, int TQ, const uint16_t* h16, int T, uint16_t* dst) {
+  const int d = TQ - T;
+  for (int t = 0; t < TQ; ++t)
+    for (int l = 0; l < N / 4; ++l)
       for (int e = 0; e < 4; ++e) {
-        const int c = 16 * (tid >> 6) + (tid & 15) + 1024 * ((tid >> 4) & 3) + 256 * e;
-        dst[(size_t)t * kN + tid * 4 + e] = t < d ? (uint16_t)0 : h16[(size_t)(t - d) * kN + c];
+        const int j = l & 15, h = (l >> 4) & 3, w = l >> 6;
+        const int c = N == kN ? 16 * w + j + 1024 * h + 256 * e
+                              : (N == 1024 ? j + 16 * h + 64 * w + 256 * e : j + 64 * h + 16 * e);
+        dst[(size_t)t * N + l * 4 + e] = t < d ? (uint16_t)0 : h16[(size_t)(t - d) * N + c];
       }
 }
 
@@ -444,10 +757,17 @@ hipError_t launch_w256(void* table, hipStream_t st) {
 
 namespace {
 
-template <int IT, bool POW>
+// NN = 4096 (three matrix-core stages) or 1024 / 256 (MfmaSmall, TQ tap
+// slots); G spectra tiles per workgroup
+template <int NN, int TQ, int IT, bool POW>
 hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st) {
   if (a.M <= 0) return hipSuccess;
-  constexpr MfmaKernel kern = mfma_kernel<IT, POW>();
+  constexpr bool big = NN == kN;
+  constexpr MfmaKernel kern = big ? mfma_kernel<IT, POW>() : mfma_small_kernel<big ? 256 : NN, TQ, IT, POW>();
+  constexpr int kN = NN;
+  constexpr int G = big ? 1 : MfmaSmall<big ? 256 : NN, TQ, 1, 0, IT, POW>::G;
+  constexpr int kLdsBytes = big ? ppf::kLdsBytes : MfmaSmall<big ? 256 : NN, TQ, 1, 0, IT, POW>::LdsBytes;
+  constexpr int kStep = big ? kTaps : TQ;     // unrolled steps per tile round
   constexpr int SB = IT == kInI8 ? 2 : 4;
   static bool attr = false;
   if (!attr) {
@@ -478,18 +798,18 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
     p.tw = (const v2f*)md.tw;
     p.w256 = (const uint32_t*)md.w256;
     p.M = (int)k;
-    // tiles of a multiple of 16 spectra (the unrolled step count), and of K
-    // when detecting, about one per CU
+    // tiles of a multiple of the unrolled step count, and of K when
+    // detecting, about one workgroup (G tiles) per CU
     const int cus = cu_count();
-    long long S = (k + cus - 1) / cus;
-    S = (S + 15) / 16 * 16;
+    long long S = (k + (long long)cus * G - 1) / ((long long)cus * G);
+    S = (S + kStep - 1) / kStep * kStep;
     if (POW) {
-      long long unit = 16;
-      while (unit % K) unit += 16;   // lcm(16, K)
+      long long unit = kStep;
+      while (unit % K) unit += kStep;   // lcm(step, K)
       S = (S + unit - 1) / unit * unit;
     }
     p.S = (int)S;
-    p.nblocks = (int)((k + S - 1) / S);
+    p.nblocks = (int)((k + S * G - 1) / (S * G));
     p.d = md.d;
     p.in_scale = md.in_scale;
     p.out_scale = md.out_scale;
@@ -500,16 +820,33 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
   return hipSuccess;
 }
 
+template <bool POW>
+hipError_t mfma_dispatch(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st) {
+  const bool f16 = md.in_type == kInF16;
+  switch (md.N) {
+    case kN:
+      return f16 ? mfma_launch<kN, 16, kInF16, POW>(md, a, pout, K, st) : mfma_launch<kN, 16, kInI8, POW>(md, a, pout, K, st);
+    case 1024:
+      if (md.tq == 8)
+        return f16 ? mfma_launch<1024, 8, kInF16, POW>(md, a, pout, K, st) : mfma_launch<1024, 8, kInI8, POW>(md, a, pout, K, st);
+      return f16 ? mfma_launch<1024, 16, kInF16, POW>(md, a, pout, K, st) : mfma_launch<1024, 16, kInI8, POW>(md, a, pout, K, st);
+    case 256:
+      if (md.tq == 8)
+        return f16 ? mfma_launch<256, 8, kInF16, POW>(md, a, pout, K, st) : mfma_launch<256, 8, kInI8, POW>(md, a, pout, K, st);
+      return f16 ? mfma_launch<256, 16, kInF16, POW>(md, a, pout, K, st) : mfma_launch<256, 16, kInI8, POW>(md, a, pout, K, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_mfma(const MfmaDev& md, const BatchArgs& a, hipStream_t st) {
-  return md.in_type == kInF16 ? mfma_launch<kInF16, false>(md, a, nullptr, 1, st)
-                              : mfma_launch<kInI8, false>(md, a, nullptr, 1, st);
+  return mfma_dispatch<false>(md, a, nullptr, 1, st);
 }
 
 hipError_t launch_mfma_power(const MfmaDev& md, const BatchArgs& a, float* pout, int K, hipStream_t st) {
-  return md.in_type == kInF16 ? mfma_launch<kInF16, true>(md, a, pout, K, st)
-                              : mfma_launch<kInI8, true>(md, a, pout, K, st);
+  return mfma_dispatch<true>(md, a, pout, K, st);
 }
 
 }  // namespace ppf

@@ -85,15 +85,18 @@ def test_plan_ex_validates_types():
 
 
 def test_matrix_core_mode_validates_its_domain():
-    """The FP16 matrix-core mode is built for N=4096 = 16^3, taps <= 16,
-    complex int8 or FP16 input and FP16 coefficients; anything else is
-    rejected before any device call."""
+    """The FP16 matrix-core mode is built for N = 256, 1024 and 4096, taps
+    <= 16, complex int8 or FP16 input and FP16 coefficients; anything else
+    is rejected before any device call."""
     L = ppf.lib()
     h16 = np.ones(4096 * 16, dtype=np.float16)
     h32 = np.ones(4096 * 16, dtype=np.float32)
     mf = ppf.PPF_FFT_MFMA_F16
     cases = [
-        (1024, 16, h16, ppf.PPF_R16, ppf.PPF_CI8),     # N is not 16^3
+        (2048, 16, h16, ppf.PPF_R16, ppf.PPF_CI8),     # N not built
+        (512, 8, h16, ppf.PPF_R16, ppf.PPF_C16),
+        (64, 4, h16, ppf.PPF_R16, ppf.PPF_CI8),
+        (1024, 17, np.ones(1024 * 17, np.float16), ppf.PPF_R16, ppf.PPF_CI8),
         (4096, 17, np.ones(4096 * 17, np.float16), ppf.PPF_R16, ppf.PPF_CI8),   # more than 16 taps
         (4096, 16, h32, ppf.PPF_R32, ppf.PPF_CI8),     # FP32 coefficients
         (4096, 16, h16, ppf.PPF_R16, ppf.PPF_C32),

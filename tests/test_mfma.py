@@ -251,3 +251,103 @@ def test_detection_in_matrix_core_mode(in_type, k_int, m_total):
     print(f"  detected power: rms rel error GPU {rel(got):.2e}, model {rel(mod):.2e}", flush=True)
     assert got.shape == ref.shape
     assert rel(got) <= 1.5 * rel(mod) + 1e-6
+
+
+# ---- N = 256 and N = 1024 on the matrix cores ------------------------------
+
+def _coeffs_n(n, taps):
+    h16, shift = signals.coeffs_fp16(signals.design_coeffs(n, taps, "hamming"))
+    return h16, shift, h16.astype(np.float64) * 2.0 ** -shift
+
+
+def _input_n(kind, n_samples, seed):
+    if kind == ppf.PPF_CI8:
+        return signals.int8_input(n_samples, seed=seed, sigma=16.0)
+    return signals.to_complex_fp16(signals.complex_gaussian(n_samples, 1.0, seed))
+
+
+@pytest.mark.parametrize("kind", [ppf.PPF_CI8, ppf.PPF_C16], ids=["ci8", "c16"])
+@pytest.mark.parametrize("n,taps,m_total", [(1024, 8, 700), (1024, 16, 333), (1024, 3, 41),
+                                            (256, 8, 2100), (256, 16, 901), (256, 1, 37)])
+def test_small_n_matches_oracle_and_model(n, taps, m_total, kind):
+    """N = 1024 (radix 4 in FP32, two DFT-16 stages on the matrix cores) and
+    N = 256 (two matrix-core stages): several tiles per workgroup group and
+    a ragged tail, against the same-input FP64 oracle at the matrix-core bar,
+    against the rounding model, and beside the FP32 DFT path."""
+    torch = _torch()
+    from tests import mfma_model
+    print(f"case mfma small N={n} T={taps} M={m_total} in={kind}", flush=True)
+    h16, shift, h_exact = _coeffs_n(n, taps)
+    x = _input_n(kind, (m_total + taps - 1) * n, seed=1300 + n + taps + kind)
+    xd = torch.from_numpy(x).cuda()
+    plan = ppf.Plan(n, taps, h16, in_type=kind, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+    assert plan.path == ppf.PPF_PATH_FUSED
+    got = plan.execute(xd)
+    plan32 = ppf.Plan(n, taps, h16, in_type=kind, coeff_shift=shift)
+    got32 = plan32.execute(xd)
+    torch.cuda.synchronize()
+    plan.close()
+    plan32.close()
+    got = got.cpu().numpy()
+    assert np.isfinite(got).all()
+    pick = sorted(set(range(0, m_total, 13)) | set(range(m_total - 20, m_total)) | {0, 1, 7, 8, 15, 16})
+    ref = oracle.ppf(x, h_exact, n, taps, spectra=pick)
+    check(got[pick], ref, f"N={n} T={taps} in={kind}")
+    mod = mfma_model.model(x, h16, shift, taps, pick)
+    agree = snr_db(got[pick], mod)
+    g32 = got32.cpu().numpy()[pick]
+    print(f"  model {snr_db(mod, ref):.2f} dB, GPU vs model {agree:.1f} dB; FP32 DFT path: SNR "
+          f"{snr_db(g32, ref):.1f} dB, max err/rms {rel_err(g32, ref):.2e}", flush=True)
+    assert abs(snr_db(got[pick], ref) - snr_db(mod, ref)) <= 0.5
+    assert agree >= 85.0
+    assert rel_err(g32, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n,kind,k_int,m_total", [(1024, ppf.PPF_CI8, 16, 640), (256, ppf.PPF_C16, 5, 300),
+                                                  (1024, ppf.PPF_C16, 3, 99)])
+def test_small_n_detection(n, kind, k_int, m_total):
+    torch = _torch()
+    from tests import mfma_model
+    taps = 8
+    print(f"case mfma small detection N={n} in={kind} K={k_int} M={m_total}", flush=True)
+    h16, shift, h_exact = _coeffs_n(n, taps)
+    x = _input_n(kind, (m_total + taps - 1) * n, seed=1500 + n + k_int)
+    plan = ppf.Plan(n, taps, h16, in_type=kind, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+    got = plan.execute_power(torch.from_numpy(x).cuda(), k_int)
+    torch.cuda.synchronize()
+    plan.close()
+    got = got.cpu().numpy().astype(np.float64)
+    ref = oracle.ppf_power(x, h_exact, n, taps, k_int)
+    mod_x = mfma_model.model(x, h16, shift, taps, range(m_total))
+    mod = (np.abs(mod_x) ** 2).reshape(m_total // k_int, k_int, n).sum(axis=1)
+    rel = lambda p: float(np.sqrt(np.mean((p - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    print(f"  detected power: rms rel error GPU {rel(got):.2e}, model {rel(mod):.2e}", flush=True)
+    assert got.shape == ref.shape
+    assert rel(got) <= 1.5 * rel(mod) + 1e-6
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_small_n_stream_chunks(n):
+    torch = _torch()
+    taps = 8
+    h16, shift, h_exact = _coeffs_n(n, taps)
+    lens = [3, 1, 17, 2, 40, 9]
+    x = signals.int8_input(sum(lens) * n, seed=91 + n, sigma=16.0)
+    plan = ppf.Plan(n, taps, h16, in_type=ppf.PPF_CI8, coeff_shift=shift, fft_mode=ppf.PPF_FFT_MFMA_F16)
+    ppf.ppf_set_stream(plan.handle, torch.cuda.current_stream().cuda_stream)
+    st = ppf.ppf_stream_create(plan.handle)
+    chunks, outs, at = [], [], 0
+    for s in lens:
+        c = x[at * n:(at + s) * n]
+        chunks.append(c)
+        xd = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+        od = torch.empty((s, n), dtype=torch.complex64, device="cuda")
+        ppf.ppf_stream_push(st, xd, od, s)
+        outs.append((xd, od))
+        at += s
+    torch.cuda.synchronize()
+    got = np.concatenate([o.cpu().numpy() for _, o in outs])
+    ppf.ppf_stream_destroy(st)
+    plan.close()
+    ref = np.concatenate(oracle.ppf_stream(chunks, h_exact, n, taps))
+    check(got, ref, f"stream N={n}")
