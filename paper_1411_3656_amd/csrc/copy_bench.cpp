@@ -2,9 +2,12 @@
 // size with the access patterns the PPF kernels use, timed with HIP events
 // after a long warm-up (clock and power state settle over tens of
 // milliseconds). Prints one JSON line per pattern:
-//   grid-stride 16-byte non-temporal copy (the fastest plain copy), and
+//   grid-stride 16-byte non-temporal copy (the fastest plain copy),
 //   tile copy: a workgroup per contiguous tile of 8 KiB blocks, 256 threads
-//   moving 8 bytes each per block (the fused kernel's block traffic).
+//   moving 8 bytes each per block (the fused kernel's block traffic),
+//   write only and read only (grid-stride, 16 bytes per lane), and
+//   expand: 2 bytes read per 8 bytes written, the traffic of complex int8
+//   input to complex FP32 spectra.
 // The byte counters of a profiled run of this program scale FETCH_SIZE and
 // WRITE_SIZE to bytes.
 
@@ -52,6 +55,30 @@ __global__ void __launch_bounds__(256) copy_tile8(const v2f* __restrict__ s, v2f
   }
 }
 
+__global__ void __launch_bounds__(256) write16(v4f* __restrict__ d, long long n) {
+  const v4f v = {1.f, 2.f, 3.f, 4.f};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    __builtin_nontemporal_store(v, d + i);
+}
+
+// the sum keeps the loads live; one value per thread is written
+__global__ void __launch_bounds__(256) read16(const v4f* __restrict__ s, v4f* __restrict__ out, long long n) {
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    acc += __builtin_nontemporal_load(s + i);
+  out[blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// element i: read 4 bytes (two int8 pairs), write 16 bytes (two FP32 pairs)
+__global__ void __launch_bounds__(256) expand4(const unsigned* __restrict__ s, v4f* __restrict__ d, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const unsigned w = __builtin_nontemporal_load(s + i);
+    const v4f v = {(float)(signed char)(w & 0xFF), (float)(signed char)((w >> 8) & 0xFF),
+                   (float)(signed char)((w >> 16) & 0xFF), (float)(signed char)(w >> 24)};
+    __builtin_nontemporal_store(v, d + i);
+  }
+}
+
 double arg_d(int argc, char** argv, const char* name, double def) {
   for (int i = 1; i + 1 < argc; ++i)
     if (!strcmp(argv[i], name)) return atof(argv[i + 1]);
@@ -79,7 +106,7 @@ int main(int argc, char** argv) {
   CK(hipEventCreate(&e1));
   const long long n16 = (long long)(bytes / 16);
   const int M = (int)(bytes / 8192);
-  auto timed = [&](const char* name, auto launch, int warmup) {
+  auto timed = [&](const char* name, auto launch, int warmup, size_t rd, size_t wr) {
     for (int i = 0; i < warmup; ++i) launch();
     CK(hipGetLastError());
     CK(hipDeviceSynchronize());
@@ -92,20 +119,29 @@ int main(int argc, char** argv) {
     ms /= reps;
     printf("{\"pattern\": \"%s\", \"bytes_read\": %zu, \"bytes_written\": %zu, \"ms_per_copy\": %.5f, "
            "\"GBps_moved\": %.1f, \"frac_of_8TBps\": %.4f}\n",
-           name, bytes, bytes, ms, 2.0 * bytes / ms / 1e6, 2.0 * bytes / ms / 1e6 / 8000.0);
+           name, rd, wr, ms, (double)(rd + wr) / ms / 1e6, (double)(rd + wr) / ms / 1e6 / 8000.0);
     fflush(stdout);
   };
   timed("stride16_grid1024", [&] {
     hipLaunchKernelGGL(copy_stride16, dim3(1024), dim3(256), 0, 0, (const v4f*)s, (v4f*)d, n16);
-  }, warm);
+  }, warm, bytes, bytes);
   for (int nb : {512, 4096}) {
     const int S = M / nb;
     char name[64];
     snprintf(name, sizeof name, "tile8_%dblocks", nb);
     timed(name, [&] {
       hipLaunchKernelGGL(copy_tile8, dim3(nb), dim3(256), 0, 0, (const v2f*)s, (v2f*)d, S, M);
-    }, 20);
+    }, 20, bytes, bytes);
   }
+  timed("write16_grid1024", [&] {
+    hipLaunchKernelGGL(write16, dim3(1024), dim3(256), 0, 0, (v4f*)d, n16);
+  }, 20, 0, bytes);
+  timed("read16_grid1024", [&] {
+    hipLaunchKernelGGL(read16, dim3(1024), dim3(256), 0, 0, (const v4f*)s, (v4f*)d, n16);
+  }, 20, bytes, (size_t)1024 * 256 * 16);
+  timed("expand_int8_to_f32_grid1024", [&] {
+    hipLaunchKernelGGL(expand4, dim3(1024), dim3(256), 0, 0, (const unsigned*)s, (v4f*)d, n16);
+  }, 20, bytes / 4, bytes);
   CK(hipFree(s));
   CK(hipFree(d));
   return 0;

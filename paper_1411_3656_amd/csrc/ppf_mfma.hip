@@ -414,7 +414,13 @@ template <int N, int TQ, int PF, int AUX, int IT, bool POW>
 struct MfmaSmall {
   static constexpr int GW = N / 256;           // waves per spectrum
   static constexpr int GL = 64 * GW;           // lanes per group
-  static constexpr int G = kThreads / GL;      // groups per workgroup
+#ifndef PPF_MFMA_SMALL_G
+#define PPF_MFMA_SMALL_G 1
+#endif
+  // groups per workgroup (each its own tile); one group per workgroup lets
+  // the workgroups on a CU pass their barriers independently
+  static constexpr int G = PPF_MFMA_SMALL_G > kThreads / GL ? kThreads / GL : PPF_MFMA_SMALL_G;
+  static constexpr int BT = G * GL;            // threads per workgroup
   static constexpr int SB = IT == kInI8 ? 2 : 4;
   static constexpr int CoefBytes = TQ * N * 2;
   static constexpr int XB = N * 4;             // one FP16 complex exchange buffer
@@ -508,7 +514,7 @@ struct MfmaSmall {
     const _Float16 b16 = (_Float16)(-1152.0f * p.in_scale);
     bias = h2{b16, b16};
 
-    for (int i = tid; i < CoefBytes / 16; i += kThreads) ((uint4*)lds)[i] = p.coef[i];
+    for (int i = tid; i < CoefBytes / 16; i += BT) ((uint4*)lds)[i] = p.coef[i];
 
     // A operands (real-part row j; inputs point 4h+e, re/im interleaved)
 #pragma unroll
@@ -677,8 +683,10 @@ struct MfmaSmall {
   }
 };
 
+// 4 waves per SIMD (128 VGPRs) whatever the workgroup size
 template <int N, int TQ, int PF, int AUX, int IT, bool POW>
-__global__ void __launch_bounds__(kThreads) ppf_mfma_small_kernel(MfmaParams p) {
+__global__ void __launch_bounds__((MfmaSmall<N, TQ, PF, AUX, IT, POW>::BT)) __attribute__((amdgpu_waves_per_eu(4)))
+ppf_mfma_small_kernel(MfmaParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds_small[];
   using E = MfmaSmall<N, TQ, PF, AUX, IT, POW>;
   const int lb = xcd_tile(blockIdx.x, p.nblocks);
@@ -768,6 +776,8 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
   constexpr int G = big ? 1 : MfmaSmall<big ? 256 : NN, TQ, 1, 0, IT, POW>::G;
   constexpr int kLdsBytes = big ? ppf::kLdsBytes : MfmaSmall<big ? 256 : NN, TQ, 1, 0, IT, POW>::LdsBytes;
   constexpr int kStep = big ? kTaps : TQ;     // unrolled steps per tile round
+  constexpr int kBlock = big ? kThreads : MfmaSmall<big ? 256 : NN, TQ, 1, 0, IT, POW>::BT;
+  constexpr int kPerCu = kThreads / kBlock;     // workgroups resident per CU (1024 threads)
   constexpr int SB = IT == kInI8 ? 2 : 4;
   static bool attr = false;
   if (!attr) {
@@ -801,7 +811,7 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
     // tiles of a multiple of the unrolled step count, and of K when
     // detecting, about one workgroup (G tiles) per CU
     const int cus = cu_count();
-    long long S = (k + (long long)cus * G - 1) / ((long long)cus * G);
+    long long S = (k + (long long)cus * kPerCu * G - 1) / ((long long)cus * kPerCu * G);
     S = (S + kStep - 1) / kStep * kStep;
     if (POW) {
       long long unit = kStep;
@@ -813,7 +823,7 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
     p.d = md.d;
     p.in_scale = md.in_scale;
     p.out_scale = md.out_scale;
-    hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kThreads), kLdsBytes, st, p);
+    hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), kLdsBytes, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
