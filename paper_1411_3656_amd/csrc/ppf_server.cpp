@@ -358,9 +358,15 @@ int class_of(ppf_server_s* s, ppf_plan_t plan) {
   ci.T = (int)v;
   ppf_plan_query(plan, PPF_Q_PATH, &v);
   ci.fused = v == PPF_PATH_FUSED;
-  // tiles of about 32K samples, 4..64 spectra
-  int ts = 32768 / ci.N;
-  ci.tile_spectra = ts < 4 ? 4 : (ts > 64 ? 64 : ts);
+  // tiles of about 32K samples, 4..64 spectra (build-time tuning)
+#ifndef PPF_SERVER_TILE_SAMPLES
+#define PPF_SERVER_TILE_SAMPLES 32768
+#endif
+#ifndef PPF_SERVER_TILE_MAX
+#define PPF_SERVER_TILE_MAX 64
+#endif
+  int ts = PPF_SERVER_TILE_SAMPLES / ci.N;
+  ci.tile_spectra = ts < 4 ? 4 : (ts > PPF_SERVER_TILE_MAX ? PPF_SERVER_TILE_MAX : ts);
   ci.max_piece = max_piece_spectra(ci);
   s->classes.push_back(ci);
   return (int)s->classes.size() - 1;
