@@ -25,7 +25,7 @@ BUILD = ROOT / "_build"
 LIB = PKG / "libppf.so"
 
 SOURCES = ["ppf_kernels.hip", "ppf_power.hip", "ppf_mfma.hip", "ppf_design.hip", "ppf_api.cpp", "ppf_server.cpp",
-           "ppf_noalloc.hip", "ppf_widen.hip"]
+           "ppf_noalloc.hip", "ppf_widen.hip", "ppf_fourstep.hip"]
 ARCH = "gfx950"
 
 COMMON = [

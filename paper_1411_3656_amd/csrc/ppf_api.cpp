@@ -127,6 +127,8 @@ struct ppf_plan_s {
   void* d_tw = nullptr;
   void* d_coef16 = nullptr;    // matrix-core mode: FP16 coefficients in lane order
   void* d_w256 = nullptr;      // matrix-core mode: FP16 values exp(-2 pi i k/256)
+  void* d_tw1 = nullptr;       // four-step two-pass form: N1- and N2-point FP32 twiddles
+  void* d_tw2 = nullptr;
   int mfma_e1 = 0;             // matrix-core mode: samples are scaled by 2^-e1
   unsigned long long id = 0;
   // Two-pass workspaces, one per HIP stream the plan has run on, so calls
@@ -203,6 +205,8 @@ struct ppf_plan_s {
     if (d2h) (void)hipStreamDestroy(d2h);
     if (d_coef16) (void)hipFree(d_coef16);
     if (d_w256) (void)hipFree(d_w256);
+    if (d_tw1) (void)hipFree(d_tw1);
+    if (d_tw2) (void)hipFree(d_tw2);
   }
 };
 
@@ -300,6 +304,14 @@ int run_batch(ppf_plan_t p, hipStream_t stream, const void* x0, long long h0, co
     }
     a.out = ws;
     a.M = k;
+    if (p->d_tw1 && p->in_type == PPF_C32) {
+      // four-step form (N = N1 * N2): FIR + N1-point transforms, then N2-point
+      hipError_t e = ppf::launch_fourstep_a(pd, a, p->d_tw1, stream);
+      if (e != hipSuccess) return fail_hip(e, "four-step pass A launch");
+      e = ppf::launch_fourstep_b(pd, ws, (char*)out + (size_t)c0 * pd.N * 8, k, p->d_tw2, stream);
+      if (e != hipSuccess) return fail_hip(e, "four-step pass B launch");
+      continue;
+    }
     hipError_t e = ppf::launch_fir(pd, a, stream);
     if (e != hipSuccess) return fail_hip(e, "FIR kernel launch");
     e = ppf::launch_fft(pd, ws, (char*)out + (size_t)c0 * pd.N * 8, k, stream);
@@ -457,6 +469,13 @@ ppf_plan_t make_plan(int N, int taps, const void* coeffs, int coeff_type, int co
   if ((e = hipMemcpy(p->d_coef, hpad.data(), hpad.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
   if ((e = hipMemcpy(p->d_ones, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) goto hip_fail;
   if ((e = ppf::launch_twiddles(p->d_tw, N, nullptr)) != hipSuccess) goto hip_fail;
+  if (ppf::fourstep_available(N, TP)) {
+    const int n1 = ppf::fourstep_n1(N), n2 = ppf::fourstep_n2(N);
+    if ((e = hipMalloc(&p->d_tw1, (size_t)n1 * 8)) != hipSuccess) { p->d_tw1 = nullptr; goto hip_fail; }
+    if ((e = hipMalloc(&p->d_tw2, (size_t)n2 * 8)) != hipSuccess) { p->d_tw2 = nullptr; goto hip_fail; }
+    if ((e = ppf::launch_twiddles(p->d_tw1, n1, nullptr)) != hipSuccess) goto hip_fail;
+    if ((e = ppf::launch_twiddles(p->d_tw2, n2, nullptr)) != hipSuccess) goto hip_fail;
+  }
   if (fft_mode == PPF_FFT_MFMA_F16) {
     // FP16 coefficients in the kernel's lane order, and the sample scale:
     // the largest FP16 stage input is at most X * g * S * 2^-e1 with

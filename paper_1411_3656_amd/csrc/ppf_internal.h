@@ -76,6 +76,15 @@ hipError_t launch_fused(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
 hipError_t launch_fir(const PlanDev& pd, const BatchArgs& a, hipStream_t st);
 // Batched N-point FFT of M contiguous blocks (in x1) to a.out.
 hipError_t launch_fft(const PlanDev& pd, const void* in, void* out, long long M, hipStream_t st);
+// Four-step two-pass form for N = N1 * N2 (N = 8192, 16384; FP32 input):
+// pass A = FIR + N1-point transforms + W_N twiddles into the workspace,
+// pass B = N2-point transforms of the workspace's columns to the spectra.
+bool fourstep_available(int N, int TP);
+int fourstep_n1(int N);
+int fourstep_n2(int N);
+hipError_t launch_fourstep_a(const PlanDev& pd, const BatchArgs& a, const void* tw_n1, hipStream_t st);
+hipError_t launch_fourstep_b(const PlanDev& pd, const void* ws, void* out, long long M, const void* tw_n2,
+                             hipStream_t st);
 // Descriptor launches with persistent grids sized for at most max_tiles
 // tiles (max_entries history entries); the counts are read on the device.
 hipError_t launch_fused_desc(const PlanDev& pd, const DescClass* cls, const TileDesc* tiles, int max_tiles,

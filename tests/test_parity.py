@@ -117,6 +117,25 @@ def test_fused_n4096(taps, m_total):
     assert np.isfinite(got).all()
 
 
+@pytest.mark.parametrize("n,taps,m_total", [(16384, 8, 300), (16384, 5, 129), (16384, 1, 77), (8192, 8, 333),
+                                            (8192, 3, 40), (8192, 2, 1)])
+def test_four_step_two_pass(n, taps, m_total):
+    """N = 8192 and 16384 with T <= 8 take the four-step two-pass form
+    (FIR + 128-point transforms of each column, then N/128-point
+    transforms): many tiles, a ragged tail and a single spectrum."""
+    idx = sorted(set(sample_spectra(m_total, taps, every=29)))
+    rng = np.random.default_rng(n + 7 * taps)
+    h32 = rng.standard_normal(taps * n).astype(np.float32)
+    x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=6000 + taps + m_total)
+    print(f"case four-step N={n} T={taps} M={m_total}", flush=True)
+    got, used = run_gpu(x, h32, n, taps, ppf.PPF_PATH_TWO_PASS)
+    assert used == ppf.PPF_PATH_TWO_PASS
+    err = rel_err(got[idx], oracle.ppf(x, h32, n, taps, spectra=idx))
+    print(f"four-step N={n} T={taps} M={m_total}: max err / rms = {err:.3e} over {len(idx)} spectra")
+    assert err <= TOL, err
+    assert np.isfinite(got).all()
+
+
 def test_c2_ska_n1024_full():
     """C2 in full: all 131,065 spectra against the oracle (computed in slices
     of spectra so its DFT matrix products stay small)."""
