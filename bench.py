@@ -37,7 +37,7 @@ PROFILES = ROOT / "profiles"
 CSRC = ROOT / "paper_1411_3656_amd" / "csrc"
 # the kernel source each workload's dominant kernel is built from
 KERNEL_SOURCES = {"c4": [CSRC / "ppf_mfma.hip"]}
-DEFAULT_KERNEL_SOURCES = [CSRC / "ppf_kernels.hip", CSRC / "ppf_engine.h"]
+DEFAULT_KERNEL_SOURCES = [CSRC / "ppf_kernels.hip", CSRC / "ppf_engine.h", CSRC / "ppf_fourstep.hip"]
 
 WORKLOADS = {
     "c1": dict(name="plain_n256_t8_16384spectra", N=256, T=8, window="hamming", spectra=16384, tones=True,
