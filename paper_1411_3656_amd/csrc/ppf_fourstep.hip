@@ -6,15 +6,17 @@
 // a column n2, takes their N1-point DFT over n1, multiplies by W_N^(n2 k1)
 // and writes the column as row n2 of a workspace Z[n2][k1]; pass B takes,
 // for each k1, the N2-point DFT over n2 of Z[.][k1] and writes X[k1 + N1 k2].
-// Each workgroup handles 8 neighbouring columns over a tile of spectra, so
-// both passes read and write 64-byte runs, hold 8 small transforms in LDS
-// (a few KiB instead of the whole spectrum) and keep several workgroups
-// per CU in flight. Traffic is that of the two-pass form: the presums make
-// one round trip through the workspace.
+// Each workgroup handles 16 neighbouring columns over a tile of spectra,
+// so both passes read and write 128-byte runs, hold 16 small transforms in
+// LDS (tens of KiB instead of the whole spectrum) and keep several
+// workgroups per CU in flight. Traffic is that of the two-pass form: the
+// presums make one round trip through the workspace.
 //
-// Lane (grp, j) of a workgroup (grp = tid % 8, j = tid / 8) owns column
-// col = col0 + grp and elements j + W e (e < 4, W = ND / 4) of its ND-point
-// transform, which is the layout of the group FFT (grp selects its plane).
+// Lane (grp, j) of a workgroup (grp = tid % G, j = tid / G, G = 16) owns
+// column col = col0 + grp and elements j + W e (e < 4, W = ND / 4) of its
+// ND-point transform, which is the layout of the group FFT (grp selects
+// its plane). A group's lanes are spread over every wavefront of the
+// workgroup, so its exchanges take block barriers.
 // Pass A, like the fused kernels, keeps a ring of TP + PF input blocks and
 // the TP coefficients of its 4 channels in registers.
 
