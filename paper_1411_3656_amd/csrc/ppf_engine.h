@@ -1093,6 +1093,13 @@ constexpr int tile_split(int N, int TP) {
   if (N == 256) return TP <= 8 ? 32 : 1;
   return 1;
 }
+// Longest tile at N = 512 and 1024 with up to 8 taps: 2 MiB of input.
+// N=1024, T=8 at 2^28 samples measured 0.868 ms with 512-spectrum (4 MiB)
+// tiles, 0.806 with 256 and 0.824 with 128; N=512 was fastest at its
+// 512-spectrum (2 MiB) tiles.
+constexpr long long tile_max_spectra(int N, int TP) {
+  return (PPF_TILE_SPLIT == 0 && (N == 512 || N == 1024) && TP <= 8) ? (2ll << 20) / (8ll * N) : 0;
+}
 
 // Largest number of spectra in one launch: block and spectrum indices stay
 // below 2^31 inside the kernels.
@@ -1124,6 +1131,7 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   static const int occ = occupancy(ki);
   const long long resident_groups = (long long)device_cus() * occ * ki.G * tile_split(N, TP);
   long long S = (a.M + resident_groups - 1) / resident_groups;
+  if (tile_max_spectra(N, TP) > 0 && S > tile_max_spectra(N, TP)) S = tile_max_spectra(N, TP);
   if (S < PPF_MIN_TILE * TP) S = PPF_MIN_TILE * TP;            // bound the tap-window re-reads
   if (POW) S = (S + K - 1) / K * K;
   const long long groups = (a.M + S - 1) / S;
