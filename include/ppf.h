@@ -167,8 +167,9 @@ int ppf_plan_query(ppf_plan_t plan, int key, long long* value);
  * PPF_ERR_INVALID). nspectra == 0 is a successful no-op; nspectra < 0 is
  * PPF_ERR_INVALID. The work goes to the calling thread's stream for the
  * plan (ppf_set_stream). Calls from several threads on one plan are safe:
- * the two-pass path keeps one device workspace (128 MiB) per HIP stream,
- * allocated on that stream's first two-pass call and freed with the plan.
+ * the two-pass path keeps one device workspace (128 MiB; 512 MiB for
+ * N >= 8192) per HIP stream, allocated on that stream's first two-pass
+ * call and freed with the plan.
  */
 int ppf_execute(ppf_plan_t plan, const void* in, void* out, long long nspectra);
 

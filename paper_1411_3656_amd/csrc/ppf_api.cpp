@@ -82,13 +82,23 @@ bool fused_ok_for(int N, int TP, int in_type) {
   return ppf::fused_available(N, TP) || TP == 1;
 }
 
-// Largest FIR workspace of the two-pass path, in bytes (stays inside the
-// 256 MB Infinity Cache between the FIR and the FFT launch of a chunk).
-// PPF_WORKSPACE_MIB overrides it at build time (tuning).
+// Largest FIR workspace of the two-pass path, in bytes: chunks of 128 MiB
+// (enough spectra per launch to fill the GPU at N <= 4096; larger chunks
+// gained nothing there), and 512 MiB for N >= 8192, where longer chunks
+// (fewer launches, longer tiles and so fewer tap-window re-reads) measured
+// faster:
+// N=16384 at 2^28 samples, T = 4, 8, 16: 1.85, 1.92, 2.07 ms with 128 MiB,
+// 1.72, 1.76, 1.84 with 512 MiB (32 and 64 MiB were slower still). Build-time
+// overrides for tuning.
 #ifndef PPF_WORKSPACE_MIB
 #define PPF_WORKSPACE_MIB 128
 #endif
-constexpr size_t kWorkspaceBytes = (size_t)PPF_WORKSPACE_MIB << 20;
+#ifndef PPF_WORKSPACE_LARGE_N_MIB
+#define PPF_WORKSPACE_LARGE_N_MIB 512
+#endif
+constexpr size_t workspace_bytes(int N) {
+  return (size_t)(N >= 8192 ? PPF_WORKSPACE_LARGE_N_MIB : PPF_WORKSPACE_MIB) << 20;
+}
 
 // Single mode: staging pairs in the copy-in / transform / copy-out pipeline
 // and the default input bytes per chunk (build-time tuning).
@@ -236,7 +246,7 @@ int ensure_workspace(ppf_plan_t p, hipStream_t st, long long min_spectra, void**
     (void)hipFree(w->ptr);
     w->ptr = nullptr;
   }
-  long long k = (long long)(kWorkspaceBytes / (8ull * p->N));
+  long long k = (long long)(workspace_bytes(p->N) / (8ull * p->N));
   if (k < min_spectra) k = min_spectra;
   if (k < 1) k = 1;
   void* d = nullptr;
