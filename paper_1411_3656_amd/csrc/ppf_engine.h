@@ -623,16 +623,6 @@ constexpr bool fused4096(int N, int TP) { return PPF_FUSED_4096 && N == 4096 && 
 // one block.
 constexpr bool fused4096_cl(int N, int TP) { return fused4096(N, TP) && TP == 8; }
 
-// Per-block engine of the fused kernel: coefficients, twiddles and lane
-// offsets are loaded once and reused by every tile the block processes.
-//
-// Ring of Q = TP + PF blocks; slot s always holds a block whose index is
-// s modulo Q (counted from the tile start). B spectra are computed per
-// step; the B blocks loaded at a step replace the B oldest, which no later
-// spectrum needs, so any Q >= TP + B - 1 is hazard-free and PF - B + 1
-// blocks of each step are loads running ahead.
-// UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
-// presum is the loaded block itself and no coefficients are held.
 // Twiddles of the wave FFT: read per stage from the table (TWG), keeping
 // the stages with one shared set in registers (TWR) (build-time tuning).
 #ifndef PPF_WF_TWG
@@ -646,6 +636,16 @@ constexpr bool fused4096_cl(int N, int TP) { return fused4096(N, TP) && TP == 8;
 #define PPF_WF_RX 16
 #endif
 
+// Per-block engine of the fused kernel: coefficients, twiddles and lane
+// offsets are loaded once and reused by every tile the block processes.
+//
+// Ring of Q = TP + PF blocks; slot s always holds a block whose index is
+// s modulo Q (counted from the tile start). B spectra are computed per
+// step; the B blocks loaded at a step replace the B oldest, which no later
+// spectrum needs, so any Q >= TP + B - 1 is hazard-free and PF - B + 1
+// blocks of each step are loads running ahead.
+// UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
+// presum is the loaded block itself and no coefficients are held.
 // WF (wave FFT): the FIR keeps its layout (R channels per lane over the
 // group), then hands the B presums of a step to LDS, and after one block
 // barrier each wavefront takes whole spectra (N/64 elements per lane) and
