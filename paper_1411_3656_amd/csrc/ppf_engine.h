@@ -280,7 +280,6 @@ struct GroupFft {
       __syncthreads();
     }
   }
-  __device__ __forceinline__ void set_lds(float* smem) { lds = smem; }
 
   __device__ __forceinline__ float* plane(int buf, int b, int reim) const {
     return lds + (((buf * B + b) * 2 + reim) * G + grp) * PL;
@@ -363,11 +362,6 @@ struct GroupFft {
     constexpr int nb = R / r;
     v2f tl[tw_fetched(S) ? stage_sets<S>() * (r - 1) : 1];
     if constexpr (tw_fetched(S)) fetch_stage_tw<S>(tl);
-    // WS: the lane index is made opaque per stage, so that the element
-    // addresses are formed where they are used instead of being held in
-    // registers across the spectrum loop
-    int jj = j;
-    if constexpr (WS && R >= 8) asm volatile("" : "+v"(jj));
     if constexpr (S > 0) {
       const int buf = DB ? par : 0;
 #pragma unroll
@@ -378,16 +372,16 @@ struct GroupFft {
 #pragma unroll
           for (int e = 0; e < R; ++e) v[b][e] = pl[rb + e * W];
         } else if constexpr (IL && WS) {
-          // swz64 is linear over GF(2) and jj (< 64) shares no bit with
-          // e*W: one lane base XORed with a constant per element
+          // swz64 is linear over GF(2) and j (< W, a power of two) shares no
+          // bit with e*W: one lane base XORed with a constant per element
           const v2f* pl = cplane(buf, b);
-          const int rb0 = swz64(jj);
+          const int rb0 = swz64(j);
 #pragma unroll
           for (int e = 0; e < R; ++e) v[b][e] = pl[rb0 ^ swz64(e * W)];
         } else if constexpr (IL) {
           const v2f* pl = cplane(buf, b);
 #pragma unroll
-          for (int e = 0; e < R; ++e) v[b][e] = pl[swz64(jj + e * W)];
+          for (int e = 0; e < R; ++e) v[b][e] = pl[swz64(j + e * W)];
         } else {
           const float* re = plane(buf, b, 0);
           const float* im = plane(buf, b, 1);
@@ -431,9 +425,9 @@ struct GroupFft {
         wbs = wb[S];
         asm volatile("" : "+v"(wbs));
       }
-      // WS: the write index of butterfly jj + i*W is a bit insertion of it,
+      // WS: the write index of butterfly j + i*W is a bit insertion of it,
       // so (with swz64 linear) one lane base XORed with a constant per write
-      const int wl = swz64((jj / Ns) * Ns * r + jj % Ns);
+      const int wl = swz64((j / Ns) * Ns * r + j % Ns);
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         float* re = plane(buf, b, 0);
@@ -445,7 +439,7 @@ struct GroupFft {
 #pragma unroll
           for (int q = 0; q < r; ++q) t[q] = v[b][i + q * nb];
           dft<r>(t);
-          const int bf = jj + i * W;
+          const int bf = j + i * W;
           const int base = (bf / Ns) * Ns * r + (bf % Ns);
 #pragma unroll
           for (int q = 0; q < r; ++q) {
@@ -623,19 +617,6 @@ constexpr bool fused4096(int N, int TP) { return PPF_FUSED_4096 && N == 4096 && 
 // one block.
 constexpr bool fused4096_cl(int N, int TP) { return fused4096(N, TP) && TP == 8; }
 
-// Twiddles of the wave FFT: read per stage from the table (TWG), keeping
-// the stages with one shared set in registers (TWR) (build-time tuning).
-#ifndef PPF_WF_TWG
-#define PPF_WF_TWG 1
-#endif
-#ifndef PPF_WF_TWR
-#define PPF_WF_TWR 0
-#endif
-// largest radix of the wave FFT's stages (build-time tuning)
-#ifndef PPF_WF_RX
-#define PPF_WF_RX 16
-#endif
-
 // Per-block engine of the fused kernel: coefficients, twiddles and lane
 // offsets are loaded once and reused by every tile the block processes.
 //
@@ -646,13 +627,8 @@ constexpr bool fused4096_cl(int N, int TP) { return fused4096(N, TP) && TP == 8;
 // blocks of each step are loads running ahead.
 // UNIT: all coefficients are one (the FFT pass of the two-pass form), so the
 // presum is the loaded block itself and no coefficients are held.
-// WF (wave FFT): the FIR keeps its layout (R channels per lane over the
-// group), then hands the B presums of a step to LDS, and after one block
-// barrier each wavefront takes whole spectra (N/64 elements per lane) and
-// transforms them alone, its exchanges synchronised within the wavefront
-// only. The spectra leave as contiguous runs of N*8 bytes per wavefront.
 template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false,
-          int IT = 0, bool WF = false>
+          int IT = 0>
 struct FusedEngine {
   static constexpr int W = N / R;
   static constexpr int SB = in_bytes(IT);   // bytes per stored input sample
@@ -670,22 +646,9 @@ struct FusedEngine {
   static constexpr bool CL = !UNIT && (TP >= 16 || fused4096_cl(N, TP));
   static constexpr size_t coef_lds_bytes() { return CL ? (size_t)TP * N * sizeof(float) : 0; }
 
-  // WF: NWV wavefronts per group, BW spectra per wavefront and step, RF
-  // elements per lane of the wavefront's transform; the hand-over planes
-  // (spectrum b of a step in plane b) are double-buffered across steps
-  static constexpr int NWV = W / 64;
-  static constexpr int BW = WF ? B / NWV : 1;
-  static constexpr int RF = WF ? N / 64 : 1;
-  static_assert(!WF || (G == 1 && !POW && !UNIT && !CL && W % 64 == 0 && B % NWV == 0), "wave FFT configuration");
-  using WFft = GroupFft<N, (WF ? N / 64 : R), (WF ? (N / 64 < PPF_WF_RX ? N / 64 : PPF_WF_RX) : RX), (WF ? NWV : G),
-                        (WF ? BW : B), false, PPF_WF_TWG != 0, PPF_WF_TWR != 0, WF>;
-  static constexpr size_t lds_bytes() {
-    return WF ? 2ull * B * N * sizeof(v2f) : Fft::lds_bytes() + coef_lds_bytes();
-  }
+  static constexpr size_t lds_bytes() { return Fft::lds_bytes() + coef_lds_bytes(); }
 
   Fft fft;
-  WFft wfft;
-  float* hand;         // WF: LDS base of the hand-over planes
   int j;
   int d;
   float hreg[(UNIT || CL) ? 1 : TP][R];
@@ -695,12 +658,7 @@ struct FusedEngine {
   __device__ __forceinline__ void init(float* smem, int grp, int j_, const float* coef, const v2f* tw, int d_) {
     j = j_;
     d = d_;
-    if constexpr (WF) {
-      hand = smem;
-      wfft.init(smem, __builtin_amdgcn_readfirstlane(j >> 6), j & 63, tw);
-    } else {
-      fft.init(smem, grp, j, tw);
-    }
+    fft.init(smem, grp, j, tw);
     if constexpr (CL) {
       float* cl = (float*)((char*)smem + Fft::lds_bytes());
       for (int i = threadIdx.x; i < TP * N; i += blockDim.x) cl[i] = coef[i];
@@ -843,35 +801,6 @@ struct FusedEngine {
               v[b][e] = acc;
             }
           }
-        if constexpr (WF) {
-          // hand the presums over: spectrum b of the step to plane b
-          v2f* hb = (v2f*)hand + (size_t)((it / B) & 1) * B * N;
-#pragma unroll
-          for (int b = 0; b < B; ++b)
-#pragma unroll
-            for (int e = 0; e < R; ++e) hb[b * N + swz64(j + e * W)] = v[b][e];
-          __syncthreads();
-          const int w = __builtin_amdgcn_readfirstlane(j >> 6);
-          const int l = j & 63;
-          wfft.set_lds((float*)hb);
-          v2f y[BW][RF];
-#pragma unroll
-          for (int bl = 0; bl < BW; ++bl)
-#pragma unroll
-            for (int e = 0; e < RF; ++e) y[bl][e] = hb[(bl * NWV + w) * N + swz64(l + e * 64)];
-          wfft.run(y);
-#pragma unroll
-          for (int bl = 0; bl < BW; ++bl) {
-            const int sidx = it + bl * NWV + w;
-            if (sidx < ng) {
-              const __amdgpu_buffer_rsrc_t rs = block_rsrc(a.out + (long long)(m0 + sidx) * N, N * (int)sizeof(v2f));
-#pragma unroll
-              for (int e = 0; e < RF; ++e)
-                buf_store<kAuxNt>(y[bl][e], rs, (uint32_t)l * (uint32_t)sizeof(v2f), (uint32_t)(e * 64 * (int)sizeof(v2f)));
-            }
-          }
-          continue;
-        }
         fft.run(v);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -917,7 +846,7 @@ struct FusedEngine {
 // Batch form: a wave of tiles of S consecutive spectra covers the batch;
 // group g of block lb owns the tile (lb*G + g).
 template <int N, int R, int RX, int G, int B, int TP, int PF, bool DB, bool TWG, bool UNIT, bool POW = false,
-          int IT = 0, bool WF = false>
+          int IT = 0>
 __global__ void __launch_bounds__((N / R) * G) __attribute__((amdgpu_waves_per_eu(PPF_SMALL16 && TP >= 16 && N <= 256 ? 2 : 1)))
 ppf_fused_kernel(FusedParams p) {
   constexpr int W = N / R;
@@ -934,7 +863,7 @@ ppf_fused_kernel(FusedParams p) {
   const int brem = p.M - blk_m0;
   const int niter = brem < p.S ? brem : p.S;                   // uniform over the block
 
-  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT, WF> eng;
+  FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT> eng;
   eng.init(smem, grp, j, p.coef, p.tw, p.d);
   TileArgs a{p.x0, p.x1, p.x1, p.out, p.h0, p.h0, p.pout, p.K};
   eng.run(a, m0, ng, niter);
@@ -1021,14 +950,6 @@ constexpr int cfg_B(int N, int TP) {
   // with 16 taps the ring already fills the register file
   return PPF_BATCH_OVERRIDE > 1 && TP <= 8 && batch_fits(N, TP, PPF_BATCH_OVERRIDE) ? PPF_BATCH_OVERRIDE : 1;
 }
-// Wave FFT (FusedEngine WF) for the spectrum kernels at N = 1024 with up
-// to 8 taps (build-time switch).
-#ifndef PPF_WAVE_FFT
-#define PPF_WAVE_FFT 0
-#endif
-constexpr bool cfg_WF(int N, int TP, bool UNIT, bool POW) {
-  return PPF_WAVE_FFT && N == 1024 && TP <= 8 && !UNIT && !POW && cfg_B(N, TP) % (cfg_W(N, TP) / 64) == 0;
-}
 constexpr bool cfg_DB(int N, int B, int TP = 1) {
   return !fused4096_cl(N, TP) && 2ull * B * 2 * cfg_G(N, TP) * plane_floats(N, cfg_W(N, TP)) * sizeof(float) <= 80 * 1024;
 }
@@ -1060,9 +981,9 @@ static int occupancy(const KernelInfo& ki) {
 template <int N, int TP, bool UNIT, bool POW = false, int IT = 0>
 static const KernelInfo& fused_info() {
   constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N), WF = cfg_WF(N, TP, UNIT, POW);
-  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT, WF>,
-                             (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT, WF>::lds_bytes()};
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N);
+  static const KernelInfo ki{(const void*)&ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>,
+                             (N / R) * G, G, FusedEngine<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>::lds_bytes()};
   return ki;
 }
 
@@ -1151,8 +1072,8 @@ static hipError_t fused_launch_one(const PlanDev& pd, const BatchArgs& a, const 
   p.pout = pout;
   p.K = K;
   constexpr int R = cfg_R(N, TP), RX = cfg_RX(N, TP), G = cfg_G(N, TP), PF = cfg_PF(N, TP), B = cfg_B(N, TP);
-  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N), WF = cfg_WF(N, TP, UNIT, POW);
-  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT, WF>), dim3((unsigned)nblocks),
+  constexpr bool DB = cfg_DB(N, B, TP), TWG = cfg_TWG(N);
+  hipLaunchKernelGGL((ppf_fused_kernel<N, R, RX, G, B, TP, PF, DB, TWG, UNIT, POW, IT>), dim3((unsigned)nblocks),
                      dim3(ki.block), ki.lds, st, p);
   return hipGetLastError();
 }
