@@ -765,6 +765,15 @@ hipError_t launch_w256(void* table, hipStream_t st) {
 
 namespace {
 
+// Tiles per resident workgroup slot: two at N = 1024 (the C2 shape at 2^27
+// samples: FP16 input 0.364 -> 0.343 ms, int8 0.296 -> 0.288 ms, same box),
+// one at N = 4096 (two measured 3% slower) and N = 256.
+// PPF_MFMA_TILE_SPLIT > 0 overrides it at build time (tuning).
+#ifndef PPF_MFMA_TILE_SPLIT
+#define PPF_MFMA_TILE_SPLIT 0
+#endif
+constexpr int mfma_tile_split(int n) { return PPF_MFMA_TILE_SPLIT > 0 ? PPF_MFMA_TILE_SPLIT : (n == 1024 ? 2 : 1); }
+
 // NN = 4096 (three matrix-core stages) or 1024 / 256 (MfmaSmall, TQ tap
 // slots); G spectra tiles per workgroup
 template <int NN, int TQ, int IT, bool POW>
@@ -811,7 +820,8 @@ hipError_t mfma_launch(const MfmaDev& md, const BatchArgs& a, float* pout, int K
     // tiles of a multiple of the unrolled step count, and of K when
     // detecting, about one workgroup (G tiles) per CU
     const int cus = cu_count();
-    long long S = (k + (long long)cus * kPerCu * G - 1) / ((long long)cus * kPerCu * G);
+    const long long slots = (long long)cus * kPerCu * G * mfma_tile_split(NN);
+    long long S = (k + slots - 1) / slots;
     S = (S + kStep - 1) / kStep * kStep;
     if (POW) {
       long long unit = kStep;
