@@ -88,3 +88,26 @@ def test_power_k_bounds():
     assert ei.value.status == ppf.PPF_ERR_UNSUPPORTED
     fused.close()
     two.close()
+
+
+@pytest.mark.parametrize("n,taps,mib", [(4096, 16, 128), (16384, 8, 512), (8192, 32, 512)])
+def test_two_pass_workspace_size(n, taps, mib):
+    """The two-pass workspace of a stream is one chunk: 128 MiB, and 512 MiB
+    for N >= 8192 (longer chunks there re-read fewer tap windows); the
+    small batch run through it still matches the oracle."""
+    torch = _torch()
+    m_total = 40
+    h = np.random.default_rng(n + taps).standard_normal(n * taps).astype(np.float32)
+    x = signals.complex_gaussian((m_total + taps - 1) * n, 1.0, seed=n + 3 * taps)
+    print(f"case workspace N={n} T={taps} M={m_total}", flush=True)
+    plan = ppf.Plan(n, taps, h)
+    try:
+        assert plan.path == ppf.PPF_PATH_TWO_PASS
+        assert ppf.ppf_plan_query(plan.handle, ppf.PPF_Q_WORKSPACE_BYTES) == 0
+        got = plan.execute(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        assert ppf.ppf_plan_query(plan.handle, ppf.PPF_Q_WORKSPACE_BYTES) == mib << 20
+        err = rel_err(got.cpu().numpy(), oracle.ppf(x, h, n, taps))
+    finally:
+        plan.close()
+    assert err <= TOL, err
